@@ -1,0 +1,89 @@
+"""Pins for the oracle's gather-scatter QQ^T (Sec. 2.3 eq. (dssum) and the
+global-to-local map Q; Sec. 3.2 gs_op contract) and its sorted maps.  CPU."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense
+from paper_2104_05829_amd import inputs
+
+
+def _structured_counts(shape, N):
+    """Closed-form counts for a structured box: unique nodes, shared nodes and
+    shared copies (a structured coordinate on an inner element boundary
+    doubles the multiplicity)."""
+    n = 1
+    unshared = 1
+    for Ea in shape:
+        n *= Ea * N + 1
+        unshared *= Ea * N + 1 - (Ea - 1)
+    E = shape[0] * shape[1] * shape[2]
+    return n, n - unshared, E * (N + 1) ** 3 - unshared
+
+
+@pytest.mark.parametrize("shape,N", [((4, 4, 4), 7), ((3, 2, 1), 3), ((2, 2, 2), 1), ((5, 1, 2), 2)])
+def test_multiplicity_and_maps(shape, N):
+    xi, _ = oracle.gll(N)
+    m = inputs.box_mesh(*shape, xi)
+    mult = oracle.multiplicity(m.gid)
+    ones = oracle.qqt(m.gid, np.ones(m.n_local))
+    np.testing.assert_array_equal(ones, mult.astype(np.float64))
+    assert set(np.unique(mult)) <= {1, 2, 4, 8}
+    perm, offs = oracle.gs_maps(m.gid)
+    n, n_shared, n_copies = _structured_counts(shape, N)
+    assert len(np.unique(m.gid)) == n
+    assert offs.size - 1 == n_shared and perm.size == n_copies
+    # definition: lexicographic (gid, local index) order of shared copies
+    g = m.gid.reshape(-1)
+    order = np.lexsort((np.arange(g.size), g))
+    keep = mult.reshape(-1)[order] >= 2
+    np.testing.assert_array_equal(perm, order[keep].astype(np.int32))
+    seg_len = np.diff(offs)
+    assert np.all(seg_len >= 2)
+    for s in range(0, offs.size - 1, max(1, offs.size // 50)):
+        grp = perm[offs[s]:offs[s + 1]]
+        assert np.all(g[grp] == g[grp[0]]) and np.all(np.diff(grp) > 0)
+
+
+def test_c1_counts_match_survey_derivation():
+    """4x4x4 elements, N=7: 24,389 unique, 6,813 shared globals, 15,192 copies."""
+    xi, _ = oracle.gll(7)
+    m = inputs.box_mesh(4, 4, 4, xi)
+    perm, offs = oracle.gs_maps(m.gid)
+    assert (len(np.unique(m.gid)), offs.size - 1, perm.size) == (24389, 6813, 15192)
+    assert int((1 - m.dirichlet).reshape(-1)[np.unique(m.gid.reshape(-1), return_index=True)[1]].sum()) == 19683
+
+
+def test_qqt_dense_and_contract():
+    """QQ^T v == Q (Q^T v) with dense Boolean Q; singletons (pointer 0) and
+    unique pointers unchanged; sum_L W QQ^T v = sum_L v."""
+    N = 3
+    xi, _ = oracle.gll(N)
+    m = inputs.box_mesh(2, 2, 1, xi, interior_zero=True)
+    g = m.gid.reshape(-1).copy()
+    # make one shared pointer unique by renumbering a single copy
+    g[5] = 10 ** 9
+    v = np.random.default_rng(11).standard_normal(g.size)
+    out = oracle.qqt(g, v)
+    Q, _ = dense.boolean_q(g)
+    np.testing.assert_allclose(out, Q @ (Q.T @ v), rtol=1e-15, atol=1e-15)
+    assert out[5] == v[5]
+    z = g == 0
+    assert z.sum() > 0
+    np.testing.assert_array_equal(out[z], v[z])
+    mult = oracle.multiplicity(g)
+    assert abs(np.sum(out / mult) - np.sum(v)) < 1e-12 * np.abs(v).sum()
+
+
+def test_qqt_sums_in_ascending_local_order():
+    """Bit-level definition used by the GPU maps: each sum starts from the
+    lowest local index and adds copies in ascending index order."""
+    g = np.array([3, 1, 3, 2, 3, 1, 0], dtype=np.int64)
+    v = np.array([1e16, 1.0, 1.0, 5.0, -1e16, 2.0, 7.0])
+    out = oracle.qqt(g, v)
+    s3 = ((0.0 + 1e16) + 1.0) + (-1e16)
+    assert out[0] == s3 and out[2] == s3 and out[4] == s3
+    assert out[1] == 3.0 and out[5] == 3.0 and out[3] == 5.0 and out[6] == 7.0
+    perm, offs = oracle.gs_maps(g)
+    np.testing.assert_array_equal(perm, [1, 5, 0, 2, 4])
+    np.testing.assert_array_equal(offs, [0, 2, 5])
