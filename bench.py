@@ -1,0 +1,268 @@
+"""Benchmark of the SEM Poisson/Helmholtz hot path on one MI355X.
+
+Step = one application of the assembled operator, sem_ax then sem_gs
+(w = QQ^T A_L u), on the 16x16x16 deformed hex box at N=7 (2,097,152 local /
+1,442,897 unique points), FP64, all six geometric factors, seeded
+uniform[-1,1] input resident in HBM.  value = unique DOFs per second.
+
+Also reported on the same JSON line:
+  roofline      the dominant kernel (the FP64 element operator) timed with HIP
+                events on the stream it runs on, algorithmic bytes / time
+                against the 8 TB/s HBM peak; HBM traffic from the rocprofv3
+                counter summary in profiles/ when it matches this kernel source
+  cpu_baseline  the CPU oracle (oracle/), timed on this host's cores on a
+                bounded sample of the same workload
+  pcg           time to a true relative residual of 1e-8 on the 32^3 deformed
+                Helmholtz box (h1=1, h2=10, N=7, 3 Gaussian right-hand sides):
+                FCG with the FP32 p-multigrid (7->3->1) against FP64 Jacobi-PCG
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GDOF/s per Ax (N=7 FP64) + PCG time-to-1e-8, mixed-prec vs FP64, %HBM peak"
+HBM_PEAK_GBS = 8000.0
+AX_BYTES_PER_POINT = 64  # u 8 + six G 48 + w 8 (FP64 Poisson)
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "ax_fp64_box16_n7_traffic.txt")
+AX_SOURCE = os.path.join(ROOT, "paper_2104_05829_amd", "csrc", "ax_impl.h")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def ax_source_sha():
+    with open(AX_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP64 element operator from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    kv = {}
+    for line in open(PROFILE_TRAFFIC):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != ax_source_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch_scaled"])
+    except (KeyError, ValueError):
+        return None
+
+
+def bench_operator(args, torch, sem_mod, inputs):
+    N = 7
+    mesh = sem_mod.box_mesh(16, 16, 16, N, deform="cyclic", amp=0.05, bc="neumann")
+    s = sem_mod.Sem(mesh)
+    inf = s.info()
+    nL, nU = inf["n_local"], inf["n_unique"]
+    u = torch.tensor(inputs.uniform_lvector(nL, 2), device="cuda")
+    w = torch.empty_like(u)
+    for _ in range(args.warmup):
+        s.ax(u, w)
+        s.gs(w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.ax(u, w)
+        s.gs(w)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    # dominant kernel alone, HIP events on the stream it is launched on
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        s.ax(u, w)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_ax = ev0.elapsed_time(ev1) / args.steps
+    ev0.record(stream)
+    for _ in range(args.steps):
+        s.gs(w)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_gs = ev0.elapsed_time(ev1) / args.steps
+    s.free()
+    return dict(mesh=mesh, nL=nL, nU=nU, ms_step=ms_step, ms_ax=ms_ax, ms_gs=ms_gs,
+                n_shared=inf["n_shared_copies"], n_seg=inf["n_segments"])
+
+
+def bench_pcg(args, torch, sem_mod, inputs):
+    """32^3 deformed box, N=7, h1=1, h2=10, homogeneous Dirichlet; 3 RHS
+    f ~ N(0,1) per node (seeds 30, 31, 32), b = QQ^T(B f) assembled on the GPU
+    with the library's own mass matrix."""
+    N = 7
+    ne = args.pcg_elems
+    mesh = sem_mod.box_mesh(ne, ne, ne, N, deform="cyclic", amp=0.05, bc="dirichlet")
+    t0 = time.perf_counter()
+    s = sem_mod.Sem(mesh, levels=(7, 3, 1))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    _, B = s.geometry()
+    W, _ = s.weights()
+    res = {"pmg": [], "jacobi": []}
+    for seed in (30, 31, 32)[: args.pcg_rhs]:
+        f = torch.tensor(inputs.gaussian_per_node(mesh.gid, seed), device="cuda")
+        b = s.gs(B * f) * (W > 0)
+        for pre in ("pmg", "jacobi"):
+            # first call builds the preconditioner (cached afterwards)
+            if not res[pre]:
+                s.solve(b, tol=1e-8, h1=1.0, h2=10.0, precond=pre, maxit=20000)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st, rc = s.solve(b, tol=1e-8, h1=1.0, h2=10.0, precond=pre, maxit=20000,
+                                coarse_tol=args.coarse_tol, coarse_maxit=args.coarse_maxit)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res[pre].append(dict(seed=seed, ms=dt * 1e3, iters=st["iters"],
+                                 true_rel_res=st["true_rel_res"], rc=rc,
+                                 coarse_iters=st["coarse_iters"], x=x))
+    # difference between the two solutions (W-weighted, relative)
+    diffs = []
+    for a, bb in zip(res["pmg"], res["jacobi"]):
+        d = float(torch.sqrt(torch.sum(W * (a["x"] - bb["x"]) ** 2) / torch.sum(W * bb["x"] ** 2)))
+        diffs.append(d)
+        a.pop("x"), bb.pop("x")
+    inf = s.info()
+    s.free()
+    out = {"workload": f"{ne}x{ne}x{ne} deformed box, N=7, Helmholtz h1=1 h2=10, "
+                       f"{args.pcg_rhs} RHS, true rel. residual 1e-8",
+           "n_unique": inf["n_unique"], "n_local": inf["n_local"], "setup_s": round(t_setup, 3)}
+    for pre in ("pmg", "jacobi"):
+        runs = res[pre]
+        out[pre] = {"ms_total": round(sum(r["ms"] for r in runs), 3),
+                    "ms_per_rhs": [round(r["ms"], 3) for r in runs],
+                    "iters": [r["iters"] for r in runs],
+                    "true_rel_res": [float(f"{r['true_rel_res']:.3e}") for r in runs],
+                    "status": [r["rc"] for r in runs]}
+        if pre == "pmg":
+            out[pre]["coarse_iters"] = [r["coarse_iters"] for r in runs]
+    out["speedup_pmg_vs_jacobi"] = round(out["jacobi"]["ms_total"] / out["pmg"]["ms_total"], 3)
+    out["rel_diff_pmg_vs_jacobi"] = [float(f"{d:.3e}") for d in diffs]
+    out["gdof_per_s_per_iter_jacobi"] = round(
+        inf["n_unique"] * sum(out["jacobi"]["iters"]) / (out["jacobi"]["ms_total"] * 1e-3) / 1e9, 3)
+    return out
+
+
+def cpu_baseline(mesh, seconds):
+    """The oracle's Ax + QQ^T on the full 16^3 N=7 mesh, repeated until
+    about `seconds` of CPU time; single-threaded C (no OpenMP)."""
+    import oracle
+    xi, _ = oracle.gll(7)
+    D = oracle.dhat(7, xi)
+    G, B, _ = oracle.geometry(7, mesh.x, mesh.y, mesh.z)
+    from paper_2104_05829_amd import inputs
+    u = inputs.uniform_lvector(mesh.n_local, 2)
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        w = oracle.ax(7, D, G, u)
+        oracle.qqt(mesh.gid, w)
+        reps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    return dt, reps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--pcg-elems", type=int, default=32)
+    ap.add_argument("--pcg-rhs", type=int, default=3)
+    ap.add_argument("--coarse-tol", type=float, default=1e-2)
+    ap.add_argument("--coarse-maxit", type=int, default=100)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2104_05829_amd import inputs
+    from paper_2104_05829_amd import sem as sem_mod
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    sem_mod.lib()  # fail loudly if the HIP library is missing
+
+    log("[bench] operator: 16^3 box, N=7, FP64 sem_ax + sem_gs")
+    op = bench_operator(args, torch, sem_mod, inputs)
+    value = op["nU"] / (op["ms_step"] * 1e-3) / 1e9
+    ax_bytes = AX_BYTES_PER_POINT * op["nL"]
+    achieved = ax_bytes / (op["ms_ax"] * 1e-3) / 1e9
+    traffic = measured_traffic()
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(op["ms_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "16x16x16 hex box, nodes perturbed by the cyclic sin(2pi.)sin(2pi.) map "
+                        "(a=0.05), N=7, FP64 sem_ax + sem_gs (Neumann operator QQ^T A_L u, six G), "
+                        "seeded uniform[-1,1] L-vector",
+            "E": 4096, "N": 7, "n_local": op["nL"], "n_unique": op["nU"],
+            "gdof_local_per_s": round(op["nL"] / (op["ms_step"] * 1e-3) / 1e9, 3),
+            "ms_ax": round(op["ms_ax"], 5), "ms_gs": round(op["ms_gs"], 5),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "ax_kernel<8,double> (FP64 Poisson element operator)",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic / 1e6, 3),
+            "traffic_unit": "MB per launch",
+            "algorithmic_bytes_per_launch": ax_bytes,
+        },
+    }
+    if not args.no_cpu:
+        log(f"[bench] cpu baseline: oracle Ax + QQ^T, about {args.cpu_seconds} s")
+        dt, reps = cpu_baseline(op["mesh"], args.cpu_seconds)
+        line["cpu_baseline"] = {
+            "value": round(op["nU"] / dt / 1e9, 6), "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} applies of the oracle's element operator + QQ^T on the full 16^3 N=7 "
+                      f"mesh, single-threaded C, {dt * 1e3:.1f} ms per apply, host "
+                      f"{os.cpu_count()} logical CPUs",
+        }
+    if not args.no_pcg:
+        log("[bench] pcg: 32^3 Helmholtz, FCG+FP32 p-MG vs FP64 Jacobi-PCG to 1e-8")
+        line["pcg"] = bench_pcg(args, torch, sem_mod, inputs)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * sem.h -- C ABI of libsem: the matrix-free spectral-element (SEM)
+ * Poisson/Helmholtz operator on hexahedral Gauss--Lobatto--Legendre (GLL)
+ * elements, its direct-stiffness summation QQ^T, and preconditioned CG around
+ * them, on one AMD Instinct MI355X (gfx950).
+ *
+ * Notation follows the NekRS paper (Fischer et al., "NekRS, a GPU-Accelerated
+ * Spectral Element Navier-Stokes Solver"), Sec. 2.3 and Sec. 3.2-3.4.
+ *
+ * Layout.  A field is an "L-vector": one value per local copy, element-major,
+ * E blocks of (N+1)^3 values, each block indexed [k][j][i] with i fastest,
+ * idx = i + (N+1) j + (N+1)^2 k + (N+1)^3 e (Sec. 2.3, eq. (uijk) with
+ * D_1 = I (x) I (x) Dh acting on i).  Device arrays hold FP64 unless stated.
+ *
+ * Ownership.  The caller owns every array it passes.  Host arrays given to
+ * sem_setup are copied and may be freed afterwards.  The handle owns the
+ * geometric factors, gather-scatter maps, weights and solver workspaces.
+ * sem_ax and sem_gs allocate nothing; sem_pcg_solve allocates its workspace
+ * on first use and keeps it in the handle.  A handle serves one call at a
+ * time (it is not re-entrant); distinct handles are independent.
+ *
+ * Streams.  Every device call takes a hipStream_t (as void*, NULL = the null
+ * stream) and enqueues its kernels on it without synchronising, except
+ * sem_setup and sem_pcg_solve, which synchronise that stream before they
+ * return.  Pointers passed to a call must stay valid until the stream reaches
+ * it.
+ *
+ * Errors.  Every function returns SEM_OK (0) or a negative code below.
+ * sem_strerror() names a code; sem_last_error() returns a thread-local text
+ * with the detail of the last failure in the calling thread.
+ */
+#ifndef SEM_H_
+#define SEM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define SEM_API __attribute__((visibility("default")))
+#else
+#define SEM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sem_handle_s *sem_handle;
+
+enum sem_status {
+    SEM_OK = 0,
+    SEM_EINVAL = -1,      /* bad argument: null pointer, size, order, option */
+    SEM_ENOMEM = -2,      /* device or host allocation failed */
+    SEM_EHIP = -3,        /* a HIP runtime call failed */
+    SEM_ENOCONV = -4,     /* solver hit maxit; x holds the last iterate */
+    SEM_EBREAKDOWN = -5,  /* p^T A p <= 0 or a NaN in the iteration */
+    SEM_EMESH = -6        /* Jacobian <= 0, or copies of one global pointer
+                             disagree in coordinates or Dirichlet flag */
+};
+
+enum sem_dtype { SEM_F64 = 0, SEM_F32 = 1 };
+enum sem_precond { SEM_PRECOND_JACOBI = 0, SEM_PRECOND_PMG = 1 };
+
+/*
+ * Mesh description (host arrays, E*(N+1)^3 entries each, L-vector layout).
+ *   x, y, z    node coordinates x^e_ijk of the isoparametric map
+ *              (Sec. 2.3, eq. (xijk)); copies of one node must agree.
+ *   gid        global pointer of each copy, >= 0 (the gs_setup contract of
+ *              Sec. 3.2): copies with equal nonzero pointers are one global
+ *              node; 0 marks a singleton (e.g. element-interior points).
+ *   dirichlet  1 on copies of nodes with homogeneous Dirichlet data, else 0;
+ *              NULL means none (pure Neumann).  This is the restriction R of
+ *              the footnote on A = R Abar R^T in Sec. 2.3.
+ */
+typedef struct {
+    int N;                     /* polynomial order, 1 <= N <= 15 */
+    int64_t E;                 /* number of elements, E*(N+1)^3 < 2^31 */
+    const double *x, *y, *z;
+    const int64_t *gid;
+    const uint8_t *dirichlet;
+} sem_mesh;
+
+/*
+ * Setup options.  pmg != 0 builds the p-multigrid hierarchy of Sec. 3.4
+ * (orders levels[0] = N > levels[1] > ... >= 1, at most 4 levels); coarse
+ * levels are rediscretised on coordinates interpolated from the fine mesh.
+ * NULL opts = no multigrid.
+ */
+typedef struct {
+    int pmg;
+    int n_levels;
+    int levels[4];
+} sem_setup_opts;
+
+/*
+ * Build a handle: GLL nodes, weights and Dh (Sec. 2.3, eq. (dh)); geometric
+ * factors G (six, eq. (gij)) and mass B = diag(rho J) (eq. (vBu)); gather-
+ * scatter maps (shared copies sorted by (global pointer, local index));
+ * multiplicity and counting weight W = 1/multiplicity (0 on Dirichlet copies).
+ * Returns SEM_EINVAL for a bad order, size or pointer, SEM_EMESH for a
+ * nonpositive Jacobian or inconsistent copies.  Synchronises `stream`.
+ */
+SEM_API int sem_setup(const sem_mesh *mesh, const sem_setup_opts *opts, void *stream, sem_handle *out);
+
+/* Release every device and host resource of the handle (NULL is a no-op). */
+SEM_API int sem_free(sem_handle h);
+
+/*
+ * Unassembled operator, Sec. 2.3 eq. (Ae):
+ *   w_L = h1 A_L(k) u_L + h2 B_L u_L,
+ *   A^e(k) = [D1;D2;D3]^T (k o G^e) [D1;D2;D3],
+ * per element, no summation across elements (that is sem_gs).
+ * u, w: device L-vectors (distinct, not overlapping).  k: device L-vector of
+ * pointwise coefficients or NULL for k = 1.  FP64.
+ */
+SEM_API int sem_ax(sem_handle h, const double *u, double *w, double h1, double h2, const double *k,
+           void *stream);
+
+/*
+ * Direct-stiffness summation v <- QQ^T v in place (Sec. 2.3 eq. (dssum) and
+ * the Q / Q^T discussion; gs_op(+) of Sec. 3.2): every copy of a global node
+ * receives the sum over all its copies; copies with pointer 0 or a unique
+ * pointer are unchanged.  Each sum adds the copies in ascending local index
+ * order, so the result is deterministic.  v: device L-vector, FP64.
+ */
+SEM_API int sem_gs(sem_handle h, double *v, void *stream);
+
+/*
+ * The same two operations at multigrid level `level` (0 = fine) in FP64 or
+ * FP32; u, w, v are level-sized device L-vectors of that dtype.  FP32 is the
+ * smoother precision of Sec. 3.4 (FP32 data and accumulation).
+ */
+SEM_API int sem_ax_level(sem_handle h, int level, int dtype, const void *u, void *w, double h1, double h2,
+                 void *stream);
+SEM_API int sem_gs_level(sem_handle h, int level, int dtype, void *v, void *stream);
+
+typedef struct {
+    double h1, h2;       /* operator h1 A(k) + h2 B (h1 = 1/Re, h2 = beta0/dt) */
+    const double *k;     /* device L-vector coefficient, NULL = 1 (Jacobi only) */
+    double tol;          /* stop when ||r||_W <= tol ||b||_W */
+    int maxit;
+    int precond;         /* SEM_PRECOND_JACOBI or SEM_PRECOND_PMG */
+    int check_every;     /* iterations between host convergence checks, >= 1 */
+    int cheb_degree;     /* Chebyshev-Jacobi degree per smoothing (PMG), e.g. 2 */
+    int lanczos_steps;   /* steps for the lambda_max estimate (PMG), e.g. 20 */
+    double cheb_lo, cheb_hi;  /* smoothing interval as fractions of lambda_max */
+    double coarse_tol;   /* coarsest-level Jacobi-PCG relative tolerance */
+    int coarse_maxit;
+    int zero_guess;      /* 1: ignore x on entry and start from 0 */
+} sem_solve_opts;
+
+typedef struct {
+    int iters;             /* outer iterations taken */
+    int converged;         /* 1 if ||r||_W <= tol ||b||_W was reached */
+    double rel_res;        /* recursive ||r||_W / ||b||_W at exit */
+    double true_rel_res;   /* ||b - A x||_W / ||b||_W recomputed in FP64 */
+    double ms_solve;       /* wall time of the iteration (host clock) */
+    double ms_setup;       /* preconditioner setup done inside this call */
+    int coarse_iters;      /* total coarsest-level iterations (PMG) */
+} sem_solve_stats;
+
+/* Fill opts with defaults: h1 = 1, h2 = 0, k = NULL, tol = 1e-8, maxit = 1000,
+ * Jacobi, check_every = 8, cheb_degree = 2, lanczos_steps = 20,
+ * interval [0.1, 1.1] lambda_max, coarse_tol = 1e-2, coarse_maxit = 100,
+ * zero_guess = 1. */
+SEM_API void sem_solve_opts_default(sem_solve_opts *opts);
+
+/*
+ * Solve R (h1 A(k) + h2 B) R^T x = R b (Sec. 2.3, eq. (aip) with the
+ * restriction footnote), on replicated L-vectors:
+ *   b  device, assembled and replicated: b = QQ^T(B_L f_L) for a load f; its
+ *      Dirichlet copies are ignored.
+ *   x  device, in: initial guess (unless opts->zero_guess), out: solution,
+ *      replicated, zero on Dirichlet copies.
+ * Jacobi: PCG with the inverse assembled diagonal.  PMG: flexible CG
+ * preconditioned by one p-multigrid V-cycle (Sec. 3.4): Chebyshev-accelerated
+ * Jacobi smoothing in FP32 on every level above the coarsest, FP64 Jacobi-PCG
+ * on the coarsest; outer iteration, inner products and coarse solve in FP64.
+ * Returns SEM_ENOCONV (x = last iterate, stats filled) when maxit is reached,
+ * SEM_EBREAKDOWN on a nonpositive curvature or NaN.  stats may be NULL.
+ * Synchronises `stream`.
+ */
+SEM_API int sem_pcg_solve(sem_handle h, const double *b, double *x, const sem_solve_opts *opts,
+                  sem_solve_stats *stats, void *stream);
+
+/*
+ * Gradient of a loss with respect to the per-copy coefficient k of
+ * A(k) = Q^T A_L(k) Q, given the forward solution u and adjoint lam
+ * (A lam = dL/du):
+ *   gk[e,q] = -h1 sum_{m,m'} (D_m lam)_q G_mm'[q] (D_m' u)_q
+ * (reference-space gradients as in eqs. (gradr)-(gradt)).  Device L-vectors.
+ */
+SEM_API int sem_grad_k(sem_handle h, const double *u, const double *lam, double h1, double *gk,
+               void *stream);
+
+/* Sizes of a level (0 = fine). */
+typedef struct {
+    int N;
+    int64_t E;
+    int64_t n_local;         /* E (N+1)^3 */
+    int64_t n_unique;        /* distinct global nodes (pointer-0 copies count once each) */
+    int64_t n_shared_copies; /* copies whose global node has 2+ copies */
+    int64_t n_segments;      /* global nodes with 2+ copies */
+    int n_levels;            /* levels in the handle */
+} sem_info_t;
+SEM_API int sem_info(sem_handle h, int level, sem_info_t *info);
+
+/*
+ * Copies of handle data into caller device buffers (for inspection and
+ * tests): perm [n_shared_copies] and offs [n_segments+1] (int32) of the sorted
+ * maps; G [6][n_local] in the order G11, G12, G13, G22, G23, G33 and B
+ * [n_local]; W [n_local] counting weight; gid [n_local] (int64) global
+ * pointers of the level.  Any output may be NULL.
+ */
+SEM_API int sem_get_maps(sem_handle h, int level, int32_t *perm, int32_t *offs, void *stream);
+SEM_API int sem_get_geometry(sem_handle h, int level, double *G, double *B, void *stream);
+SEM_API int sem_get_weights(sem_handle h, int level, double *W, int64_t *gid, void *stream);
+
+/* GLL nodes xi[N+1], weights rho[N+1] and Dh[(N+1)^2] (row = point) of the
+ * library, on the host (any output may be NULL).  No device work. */
+SEM_API int sem_gll(int N, double *xi, double *rho, double *D);
+
+SEM_API const char *sem_strerror(int code);
+SEM_API const char *sem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEM_H_ */

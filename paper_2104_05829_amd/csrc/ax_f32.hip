@@ -1,0 +1,8 @@
+// F32 instantiation of the element operator (see ax_impl.h).
+#include "ax_impl.h"
+
+namespace semx {
+template int launch_ax<float>(const Level &, const float *, const float *, const float *, const float *,
+                            float *, double, double, const float *, double *, int64_t *, hipStream_t,
+                            const int *);
+}  // namespace semx

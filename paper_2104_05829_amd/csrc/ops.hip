@@ -1,0 +1,265 @@
+// Gather-scatter, geometry, operator diagonal, dL/dk and transfer kernels.
+#include "sem_internal.h"
+
+namespace semx {
+
+// ---------------------------------------------------------------------------
+// QQ^T (Sec. 2.3 eq. (dssum); gs_op(+) of Sec. 3.2) over the sorted maps: one
+// thread per shared global node (segment).  The copies of a segment are listed
+// in ascending local index, the sum starts from 0 and adds them in that order,
+// then every copy receives it.  Unshared copies are never touched.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void gs_kernel(int64_t nseg, const int32_t *__restrict__ perm,
+                          const int32_t *__restrict__ offs, T *__restrict__ v,
+                          const int *__restrict__ skip)
+{
+    if (skip != nullptr && *skip != 0) return;
+    const int64_t sidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sidx >= nseg) return;
+    const int a = offs[sidx], b = offs[sidx + 1];
+    T acc = T(0);
+    for (int o = a; o < b; ++o) acc += v[perm[o]];
+    for (int o = a; o < b; ++o) v[perm[o]] = acc;
+}
+
+template <typename T>
+int launch_gs(const Level &L, T *v, hipStream_t s, const int *skip)
+{
+    if (L.nseg == 0) return SEM_OK;
+    const int bs = 256;
+    const int64_t nb = (L.nseg + bs - 1) / bs;
+    hipLaunchKernelGGL(gs_kernel<T>, dim3((unsigned)nb), dim3(bs), 0, s, L.nseg, L.perm, L.offs, v, skip);
+    SEM_HIP(hipGetLastError());
+    return SEM_OK;
+}
+template int launch_gs<double>(const Level &, double *, hipStream_t, const int *);
+template int launch_gs<float>(const Level &, float *, hipStream_t, const int *);
+
+// ---------------------------------------------------------------------------
+// Geometric factors (Sec. 2.3 eqs. (grad), (vBu), (gij)): one block per
+// element, one thread per point.  dx_p/dr_q = D_q x_p; J = det; dr/dx from the
+// adjugate; B = rho_i rho_j rho_k J; G_mm' = (sum_l dr_m/dx_l dr_m'/dx_l) B.
+// G is written element-blocked [E][6][np].  bad is set when J <= 0.
+// ---------------------------------------------------------------------------
+__global__ void geometry_kernel(int64_t E, int nq, const double *__restrict__ x,
+                                const double *__restrict__ y, const double *__restrict__ z,
+                                const double *__restrict__ D, const double *__restrict__ rho,
+                                double *__restrict__ G, double *__restrict__ B, int *bad)
+{
+    const int64_t e = blockIdx.x;
+    const int np = nq * nq * nq;
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+        const int i = p % nq, j = (p / nq) % nq, k = p / (nq * nq);
+        const double *xs[3] = {x + e * np, y + e * np, z + e * np};
+        double M[3][3];  // M[a][q] = d x_a / d r_q
+        for (int a = 0; a < 3; ++a) {
+            double dr = 0, ds = 0, dt = 0;
+            for (int l = 0; l < nq; ++l) {
+                dr += D[i * nq + l] * xs[a][l + nq * (j + nq * k)];
+                ds += D[j * nq + l] * xs[a][i + nq * (l + nq * k)];
+                dt += D[k * nq + l] * xs[a][i + nq * (j + nq * l)];
+            }
+            M[a][0] = dr;
+            M[a][1] = ds;
+            M[a][2] = dt;
+        }
+        // adjugate: C[q][a] = cofactor of M[a][q]; (dr/dx)[q][a] = C[q][a] / J
+        double C[3][3];
+        C[0][0] = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+        C[0][1] = M[0][2] * M[2][1] - M[0][1] * M[2][2];
+        C[0][2] = M[0][1] * M[1][2] - M[0][2] * M[1][1];
+        C[1][0] = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+        C[1][1] = M[0][0] * M[2][2] - M[0][2] * M[2][0];
+        C[1][2] = M[0][2] * M[1][0] - M[0][0] * M[1][2];
+        C[2][0] = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+        C[2][1] = M[0][1] * M[2][0] - M[0][0] * M[2][1];
+        C[2][2] = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+        const double J = M[0][0] * C[0][0] + M[0][1] * C[1][0] + M[0][2] * C[2][0];
+        if (!(J > 0.0)) atomicOr(bad, 1);
+        const double w = rho[i] * rho[j] * rho[k] * J;
+        B[e * np + p] = w;
+        // G_mm' = sum_a (C[m][a]/J)(C[m'][a]/J) rho J = sum_a C[m][a] C[m'][a] rho / J
+        const double sc = rho[i] * rho[j] * rho[k] / J;
+        double *Ge = G + e * 6 * np + p;
+        int slot = 0;
+        for (int m = 0; m < 3; ++m)
+            for (int mp = m; mp < 3; ++mp) {
+                const double g = C[m][0] * C[mp][0] + C[m][1] * C[mp][1] + C[m][2] * C[mp][2];
+                Ge[slot * np] = g * sc;
+                ++slot;
+            }
+    }
+}
+
+int launch_geometry(const Level &L, const double *x, const double *y, const double *z, double *G,
+                    double *B, int *bad, hipStream_t s)
+{
+    // rho lives right after D in the level's D buffer (see setup)
+    const double *rho = L.D + L.nq * L.nq;
+    const int bs = L.np >= 256 ? 256 : ((L.np + 63) / 64) * 64;
+    hipLaunchKernelGGL(geometry_kernel, dim3((unsigned)L.E), dim3(bs), 0, s, L.E, L.nq, x, y, z,
+                       L.D, rho, G, B, bad);
+    SEM_HIP(hipGetLastError());
+    return SEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal of the unassembled h1 A^e(k) + h2 B^e: for m = m' the sum of
+// Dh[l][i]^2 G_mm over the line, for m != m' only the point itself couples
+// (D_m and D_m' share a nonzero only on the diagonal).
+// ---------------------------------------------------------------------------
+__global__ void diag_kernel(int64_t nL, int nq, const double *__restrict__ G,
+                            const double *__restrict__ B, const double *__restrict__ kc,
+                            const double *__restrict__ D, double h1, double h2,
+                            double *__restrict__ d)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nL) return;
+    const int np = nq * nq * nq;
+    const int64_t e = q / np;
+    const int p = (int)(q - e * np);
+    const int i = p % nq, j = (p / nq) % nq, k = p / (nq * nq);
+    const double *Ge = G + e * 6 * np;
+    const double *ke = kc ? kc + e * np : nullptr;
+    double s = 0.0;
+    for (int l = 0; l < nq; ++l) {
+        const int pi = l + nq * (j + nq * k), pj = i + nq * (l + nq * k), pk = i + nq * (j + nq * l);
+        s += D[l * nq + i] * D[l * nq + i] * Ge[0 * np + pi] * (ke ? ke[pi] : 1.0);
+        s += D[l * nq + j] * D[l * nq + j] * Ge[3 * np + pj] * (ke ? ke[pj] : 1.0);
+        s += D[l * nq + k] * D[l * nq + k] * Ge[5 * np + pk] * (ke ? ke[pk] : 1.0);
+    }
+    const double c = ke ? ke[p] : 1.0;
+    const double di = D[i * nq + i], dj = D[j * nq + j], dk = D[k * nq + k];
+    s += 2.0 * c * (di * dj * Ge[1 * np + p] + di * dk * Ge[2 * np + p] + dj * dk * Ge[4 * np + p]);
+    double v = h1 * s;
+    if (h2 != 0.0) v += h2 * B[q];
+    d[q] = v;
+}
+
+template <typename T>
+int launch_diag(const Level &L, const double *k, double h1, double h2, double *d, hipStream_t s)
+{
+    const int bs = 256;
+    const int64_t nb = (L.nL + bs - 1) / bs;
+    hipLaunchKernelGGL(diag_kernel, dim3((unsigned)nb), dim3(bs), 0, s, L.nL, L.nq, L.G, L.B, k,
+                       L.D, h1, h2, d);
+    SEM_HIP(hipGetLastError());
+    return SEM_OK;
+}
+template int launch_diag<double>(const Level &, const double *, double, double, double *,
+                                 hipStream_t);
+
+// ---------------------------------------------------------------------------
+// dL/dk per copy: -h1 (D lam)^T G (D u), reference-space gradients of both
+// fields at the point (eqs. (gradr)-(gradt)) contracted with G.
+// ---------------------------------------------------------------------------
+__global__ void grad_k_kernel(int64_t nL, int nq, const double *__restrict__ G,
+                              const double *__restrict__ D, const double *__restrict__ u,
+                              const double *__restrict__ lam, double h1, double *__restrict__ gk)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nL) return;
+    const int np = nq * nq * nq;
+    const int64_t e = q / np;
+    const int p = (int)(q - e * np);
+    const int i = p % nq, j = (p / nq) % nq, k = p / (nq * nq);
+    const double *ue = u + e * np, *le = lam + e * np;
+    double a0 = 0, a1 = 0, a2 = 0, c0 = 0, c1 = 0, c2 = 0;
+    for (int l = 0; l < nq; ++l) {
+        const int pi = l + nq * (j + nq * k), pj = i + nq * (l + nq * k), pk = i + nq * (j + nq * l);
+        a0 += D[i * nq + l] * le[pi];
+        a1 += D[j * nq + l] * le[pj];
+        a2 += D[k * nq + l] * le[pk];
+        c0 += D[i * nq + l] * ue[pi];
+        c1 += D[j * nq + l] * ue[pj];
+        c2 += D[k * nq + l] * ue[pk];
+    }
+    const double *Ge = G + e * 6 * np + p;
+    const double g11 = Ge[0], g12 = Ge[np], g13 = Ge[2 * np], g22 = Ge[3 * np], g23 = Ge[4 * np],
+                 g33 = Ge[5 * np];
+    const double s = a0 * (g11 * c0 + g12 * c1 + g13 * c2) + a1 * (g12 * c0 + g22 * c1 + g23 * c2)
+                   + a2 * (g13 * c0 + g23 * c1 + g33 * c2);
+    gk[q] = -h1 * s;
+}
+
+int launch_grad_k(const Level &L, const double *u, const double *lam, double h1, double *gk,
+                  hipStream_t s)
+{
+    const int bs = 256;
+    const int64_t nb = (L.nL + bs - 1) / bs;
+    hipLaunchKernelGGL(grad_k_kernel, dim3((unsigned)nb), dim3(bs), 0, s, L.nL, L.nq, L.G, L.D, u,
+                       lam, h1, gk);
+    SEM_HIP(hipGetLastError());
+    return SEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise tensor-product interpolation between orders, sum-factorised in
+// three LDS passes: out = (J (x) J (x) J) in with J [nt][ns] (transpose=false),
+// or out = (J^T (x) J^T (x) J^T) in with J [ns][nt] stored as [nt_in][ns_out]
+// (transpose=true, the restriction).  One block per element.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void interp_kernel(int64_t E, int ns, int nt, const T *__restrict__ J, bool transpose,
+                              const T *__restrict__ in, T *__restrict__ out)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *sin = reinterpret_cast<T *>(smem_raw);            // ns^3
+    T *t1 = sin + ns * ns * ns;                          // ns*ns*nt  [c][b][i]
+    T *t2 = t1 + ns * ns * nt;                           // ns*nt*nt  [c][j][i]
+    __shared__ T sJ[16 * 16];
+    const int64_t e = blockIdx.x;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    // matrix A [nt][ns]: A[a][b] = J[a][b] or J[b][a] (J given as [ns][nt] then)
+    for (int t = tid; t < nt * ns; t += nth) {
+        const int a = t / ns, b = t % ns;
+        sJ[t] = transpose ? J[b * nt + a] : J[a * ns + b];
+    }
+    const int pin = ns * ns * ns, pout = nt * nt * nt;
+    for (int t = tid; t < pin; t += nth) sin[t] = in[e * pin + t];
+    __syncthreads();
+    for (int t = tid; t < ns * ns * nt; t += nth) {
+        const int i = t % nt, b = (t / nt) % ns, c = t / (nt * ns);
+        T s = 0;
+        for (int a = 0; a < ns; ++a) s += sJ[i * ns + a] * sin[a + ns * (b + ns * c)];
+        t1[t] = s;
+    }
+    __syncthreads();
+    for (int t = tid; t < ns * nt * nt; t += nth) {
+        const int i = t % nt, j = (t / nt) % nt, c = t / (nt * nt);
+        T s = 0;
+        for (int b = 0; b < ns; ++b) s += sJ[j * ns + b] * t1[i + nt * (b + ns * c)];
+        t2[t] = s;
+    }
+    __syncthreads();
+    for (int t = tid; t < pout; t += nth) {
+        const int i = t % nt, j = (t / nt) % nt, k = t / (nt * nt);
+        T s = 0;
+        for (int c = 0; c < ns; ++c) s += sJ[k * ns + c] * t2[i + nt * (j + nt * c)];
+        out[e * pout + t] = s;
+    }
+}
+
+template <typename T>
+int launch_interp(int64_t E, int ns, int nt, const T *J, const T *in, T *out, bool transpose,
+                  hipStream_t s)
+{
+    if (ns > 16 || nt > 16) {
+        set_error("interp: order too large");
+        return SEM_EINVAL;
+    }
+    const size_t shm = sizeof(T) * ((size_t)ns * ns * ns + (size_t)ns * ns * nt + (size_t)ns * nt * nt);
+    const int pout = nt * nt * nt;
+    const int bs = pout >= 256 ? 256 : ((pout + 63) / 64) * 64;
+    hipLaunchKernelGGL(interp_kernel<T>, dim3((unsigned)E), dim3(bs), shm, s, E, ns, nt, J,
+                       transpose, in, out);
+    SEM_HIP(hipGetLastError());
+    return SEM_OK;
+}
+template int launch_interp<double>(int64_t, int, int, const double *, const double *, double *,
+                                   bool, hipStream_t);
+template int launch_interp<float>(int64_t, int, int, const float *, const float *, float *, bool,
+                                  hipStream_t);
+
+}  // namespace semx

@@ -1,0 +1,154 @@
+// Internal declarations of libsem (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/sem.h"
+
+namespace semx {
+
+// thread-local detail text for sem_last_error()
+void set_error(const char *fmt, ...);
+
+#define SEM_HIP(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            ::semx::set_error("%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,    \
+                              __LINE__);                                                   \
+            return SEM_EHIP;                                                               \
+        }                                                                                  \
+    } while (0)
+
+#define SEM_TRY(expr)                        \
+    do {                                     \
+        int rc_ = (expr);                    \
+        if (rc_ != SEM_OK) return rc_;       \
+    } while (0)
+
+constexpr int kMaxN = 15;
+constexpr int kMaxLevels = 4;
+
+// Device scalars of one Krylov solve (kept on the device between kernels).
+struct KrylovScalars {
+    double rz;      // (r, z)_W of the current iterate
+    double rz_old;  // previous (r, z)_W (flexible CG)
+    double pw;      // (p, A p)_W
+    double zw;      // (z_new, A p)_W (flexible CG Polak-Ribiere term)
+    double alpha;
+    double beta;
+    double rr;      // (r, r)_W
+    double bb;      // (b, b)_W
+    double tol2;    // tol^2 (b, b)_W
+    int iters;
+    int done;       // 1 once converged or failed; later kernels become no-ops
+    int status;     // SEM_OK / SEM_EBREAKDOWN
+    int maxit;
+};
+
+// One polynomial order of the discretisation on the handle's mesh.
+struct Level {
+    int N = 0, nq = 0, np = 0;
+    int64_t E = 0, nL = 0;
+    int64_t n_unique = 0, ncopies = 0, nseg = 0;
+    // geometry: G element-blocked [E][6][np] (G11,G12,G13,G22,G23,G33), B [nL]
+    double *G = nullptr, *B = nullptr;
+    float *G32 = nullptr, *B32 = nullptr;
+    double *W = nullptr;   // counting weight, 0 on Dirichlet copies
+    float *W32 = nullptr;
+    int64_t *gid = nullptr;
+    uint8_t *dir = nullptr;
+    int32_t *perm = nullptr, *offs = nullptr;
+    double *D = nullptr;   // Dh [nq][nq] (row = point)
+    float *D32 = nullptr;
+    // interpolation from the next coarser level's nodes to this level's
+    // points: J [nq][nq_coarse]; null on the coarsest level
+    double *Jc = nullptr;
+    float *Jc32 = nullptr;
+    // per-operator preconditioner data
+    double *Dinv = nullptr;
+    float *Dinv32 = nullptr;
+    double lmax = 0.0;
+};
+
+struct Workspace {
+    int64_t nL = 0;
+    // FP64 outer vectors
+    double *r = nullptr, *p = nullptr, *w = nullptr, *z = nullptr;
+    // reduction partials and scalars
+    double *partial = nullptr;
+    int64_t n_partial = 0;
+    KrylovScalars *sc = nullptr;      // outer
+    KrylovScalars *sc_c = nullptr;    // coarse
+    KrylovScalars *host_sc = nullptr; // pinned mirror
+    // multigrid per-level vectors (FP32 on smoother levels, FP64 on the coarsest)
+    void *mg_r[kMaxLevels] = {}, *mg_x[kMaxLevels] = {}, *mg_t[kMaxLevels] = {},
+         *mg_d[kMaxLevels] = {}, *mg_s[kMaxLevels] = {};
+    double *c_r = nullptr, *c_p = nullptr, *c_w = nullptr;  // coarse CG
+};
+
+struct PrecondKey {
+    bool valid = false;
+    double h1 = 0, h2 = 0;
+    int precond = -1;
+    int cheb_degree = 0, lanczos_steps = 0;
+    double lo = 0, hi = 0;
+};
+
+}  // namespace semx
+
+struct sem_handle_s {
+    int device = 0;
+    int n_levels = 0;
+    semx::Level lv[semx::kMaxLevels];
+    semx::Workspace ws;
+    semx::PrecondKey key;
+    uint64_t lanczos_seed = 0x5eed5eedULL;
+};
+
+namespace semx {
+
+// ---- kernels (launchers) ------------------------------------------------
+// Element operator w = h1 A_L(k) u + h2 B u on a level; optional per-block
+// partial sums of u.w written to `partial` (one per block, count returned via
+// *nblocks).  T = double or float.
+// `skip` (nullable): device flag; when nonzero at launch time the kernel does
+// nothing (used to turn the tail of an enqueued iteration batch into no-ops).
+template <typename T>
+int launch_ax(const Level &L, const T *G, const T *B, const T *D, const T *u, T *w, double h1,
+              double h2, const T *k, double *partial, int64_t *nblocks, hipStream_t s,
+              const int *skip = nullptr);
+
+template <typename T>
+int launch_gs(const Level &L, T *v, hipStream_t s, const int *skip = nullptr);
+
+int launch_geometry(const Level &L, const double *x, const double *y, const double *z,
+                    double *G, double *B, int *bad, hipStream_t s);
+
+template <typename T>
+int launch_diag(const Level &L, const double *k, double h1, double h2, double *d, hipStream_t s);
+
+int launch_grad_k(const Level &L, const double *u, const double *lam, double h1, double *gk,
+                  hipStream_t s);
+
+// elementwise tensor-product interpolation out = (J (x) J (x) J) in, J [nt][ns]
+template <typename T>
+int launch_interp(int64_t E, int ns, int nt, const T *J, const T *in, T *out, bool transpose,
+                  hipStream_t s);
+
+// setup helpers
+int build_maps(Level &L, const int64_t *gid_dev, const uint8_t *dir_dev, const double *x,
+               const double *y, const double *z, int *bad_dev, hipStream_t s);
+
+int host_gll(int N, double *xi, double *rho, double *D);
+void host_interp(int ns, const double *xs, int nt, const double *xt, double *J);
+
+// solver entry (solve.hip)
+int pcg_solve(sem_handle h, const double *b, double *x, const sem_solve_opts *o,
+              sem_solve_stats *st, hipStream_t s);
+void free_workspace(sem_handle h);
+
+}  // namespace semx

@@ -1,0 +1,323 @@
+"""Thin Python binding of libsem (include/sem.h).
+
+Argument marshalling only: every step runs in the HIP library.  Device arrays
+are torch tensors on the current GPU; the HIP stream is torch's current
+stream.  The library must be built (``__graft_entry__.build()`` or
+``python -m paper_2104_05829_amd.build``); importing works without it, every
+call fails loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import inputs
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsem.so")
+
+SEM_OK, SEM_EINVAL, SEM_ENOMEM, SEM_EHIP, SEM_ENOCONV, SEM_EBREAKDOWN, SEM_EMESH = 0, -1, -2, -3, -4, -5, -6
+SEM_F64, SEM_F32 = 0, 1
+SEM_PRECOND_JACOBI, SEM_PRECOND_PMG = 0, 1
+
+c_double_p = ctypes.POINTER(ctypes.c_double)
+
+
+class SemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(msg)
+        self.code = code
+
+
+class SemMesh(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("E", ctypes.c_int64), ("x", ctypes.c_void_p),
+                ("y", ctypes.c_void_p), ("z", ctypes.c_void_p), ("gid", ctypes.c_void_p),
+                ("dirichlet", ctypes.c_void_p)]
+
+
+class SemSetupOpts(ctypes.Structure):
+    _fields_ = [("pmg", ctypes.c_int), ("n_levels", ctypes.c_int), ("levels", ctypes.c_int * 4)]
+
+
+class SemSolveOpts(ctypes.Structure):
+    _fields_ = [("h1", ctypes.c_double), ("h2", ctypes.c_double), ("k", ctypes.c_void_p),
+                ("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("precond", ctypes.c_int),
+                ("check_every", ctypes.c_int), ("cheb_degree", ctypes.c_int),
+                ("lanczos_steps", ctypes.c_int), ("cheb_lo", ctypes.c_double),
+                ("cheb_hi", ctypes.c_double), ("coarse_tol", ctypes.c_double),
+                ("coarse_maxit", ctypes.c_int), ("zero_guess", ctypes.c_int)]
+
+
+class SemSolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("rel_res", ctypes.c_double),
+                ("true_rel_res", ctypes.c_double), ("ms_solve", ctypes.c_double),
+                ("ms_setup", ctypes.c_double), ("coarse_iters", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class SemInfo(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("E", ctypes.c_int64), ("n_local", ctypes.c_int64),
+                ("n_unique", ctypes.c_int64), ("n_shared_copies", ctypes.c_int64),
+                ("n_segments", ctypes.c_int64), ("n_levels", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# every symbol the header declares, with its ctypes signature
+_VP = ctypes.c_void_p
+_SIGS = {
+    "sem_setup": (ctypes.c_int, [ctypes.POINTER(SemMesh), ctypes.POINTER(SemSetupOpts), _VP,
+                                 ctypes.POINTER(_VP)]),
+    "sem_free": (ctypes.c_int, [_VP]),
+    "sem_ax": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, ctypes.c_double, _VP, _VP]),
+    "sem_gs": (ctypes.c_int, [_VP, _VP, _VP]),
+    "sem_ax_level": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, _VP, ctypes.c_double,
+                                    ctypes.c_double, _VP]),
+    "sem_gs_level": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, _VP]),
+    "sem_solve_opts_default": (None, [ctypes.POINTER(SemSolveOpts)]),
+    "sem_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(SemSolveOpts),
+                                     ctypes.POINTER(SemSolveStats), _VP]),
+    "sem_grad_k": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
+    "sem_info": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(SemInfo)]),
+    "sem_get_maps": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
+    "sem_get_geometry": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
+    "sem_get_weights": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
+    "sem_gll": (ctypes.c_int, [ctypes.c_int, _VP, _VP, _VP]),
+    "sem_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "sem_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libsem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "or python -m paper_2104_05829_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != SEM_OK:
+        L = lib()
+        raise SemError(rc, f"{what}: {L.sem_strerror(rc).decode()} -- {L.sem_last_error().decode()}")
+
+
+def gll(N: int):
+    """The library's GLL nodes, weights and Dh (host)."""
+    xi = np.zeros(N + 1)
+    rho = np.zeros(N + 1)
+    D = np.zeros((N + 1) * (N + 1))
+    _check(lib().sem_gll(N, xi.ctypes.data, rho.ctypes.data, D.ctypes.data), "sem_gll")
+    return xi, rho, D.reshape(N + 1, N + 1)
+
+
+def box_mesh(ex, ey, ez, N, **kw) -> inputs.BoxMesh:
+    """Box mesh on the library's own GLL nodes (see inputs.box_mesh)."""
+    xi, _, _ = gll(N)
+    return inputs.box_mesh(ex, ey, ez, xi, **kw)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, dtype, n, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Sem:
+    """A libsem handle on the current GPU.
+
+    mesh: an inputs.BoxMesh (or any object with N, E, x, y, z, gid, dirichlet
+    host arrays in L-vector layout).  levels: p-multigrid orders, e.g.
+    (7, 3, 1); None for no multigrid.
+    """
+
+    def __init__(self, mesh, levels=None):
+        torch = _torch()
+        L = lib()
+        self.N = int(mesh.N)
+        nq = self.N + 1
+        self._x = np.ascontiguousarray(mesh.x, dtype=np.float64).reshape(-1)
+        self._y = np.ascontiguousarray(mesh.y, dtype=np.float64).reshape(-1)
+        self._z = np.ascontiguousarray(mesh.z, dtype=np.float64).reshape(-1)
+        self._g = np.ascontiguousarray(mesh.gid, dtype=np.int64).reshape(-1)
+        dirichlet = getattr(mesh, "dirichlet", None)
+        self._d = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8).reshape(-1)
+        self.E = self._x.size // nq ** 3
+        self.n_local = self._x.size
+        m = SemMesh(self.N, self.E, self._x.ctypes.data, self._y.ctypes.data, self._z.ctypes.data,
+                    self._g.ctypes.data, None if self._d is None else self._d.ctypes.data)
+        opts = SemSetupOpts(0, 1, (ctypes.c_int * 4)(self.N, 0, 0, 0))
+        if levels is not None and len(levels) > 1:
+            lv = list(levels) + [0] * (4 - len(levels))
+            opts = SemSetupOpts(1, len(levels), (ctypes.c_int * 4)(*lv))
+        self.levels = tuple(levels) if levels is not None else (self.N,)
+        h = ctypes.c_void_p()
+        self.device = torch.cuda.current_device()
+        _check(L.sem_setup(ctypes.byref(m), ctypes.byref(opts), _stream(), ctypes.byref(h)), "sem_setup")
+        self._h = h
+        self.info0 = self.info(0)
+
+    # -- lifecycle --------------------------------------------------------
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sem_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def _handle(self):
+        if self._h is None or not self._h.value:
+            raise RuntimeError("handle freed")
+        return self._h
+
+    # -- operator and gather-scatter ---------------------------------------
+    def ax(self, u, w=None, h1=1.0, h2=0.0, k=None):
+        torch = _torch()
+        if w is None:
+            w = torch.empty_like(u)
+        pu = _dev_ptr(u, torch.float64, self.n_local, "u")
+        pw = _dev_ptr(w, torch.float64, self.n_local, "w")
+        pk = None if k is None else _dev_ptr(k, torch.float64, self.n_local, "k")
+        _check(lib().sem_ax(self._handle(), pu, pw, float(h1), float(h2), pk, _stream()), "sem_ax")
+        return w
+
+    def gs(self, v):
+        torch = _torch()
+        pv = _dev_ptr(v, torch.float64, self.n_local, "v")
+        _check(lib().sem_gs(self._handle(), pv, _stream()), "sem_gs")
+        return v
+
+    def ax_level(self, level, u, w=None, h1=1.0, h2=0.0):
+        torch = _torch()
+        if w is None:
+            w = torch.empty_like(u)
+        dt = SEM_F64 if u.dtype == torch.float64 else SEM_F32
+        n = self.info(level)["n_local"]
+        pu = _dev_ptr(u, u.dtype, n, "u")
+        pw = _dev_ptr(w, u.dtype, n, "w")
+        _check(lib().sem_ax_level(self._handle(), level, dt, pu, pw, float(h1), float(h2), _stream()),
+               "sem_ax_level")
+        return w
+
+    def gs_level(self, level, v):
+        torch = _torch()
+        dt = SEM_F64 if v.dtype == torch.float64 else SEM_F32
+        n = self.info(level)["n_local"]
+        pv = _dev_ptr(v, v.dtype, n, "v")
+        _check(lib().sem_gs_level(self._handle(), level, dt, pv, _stream()), "sem_gs_level")
+        return v
+
+    def grad_k(self, u, lam, h1=1.0, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(u)
+        _check(lib().sem_grad_k(self._handle(), _dev_ptr(u, torch.float64, self.n_local, "u"),
+                                _dev_ptr(lam, torch.float64, self.n_local, "lam"), float(h1),
+                                _dev_ptr(out, torch.float64, self.n_local, "gk"), _stream()),
+               "sem_grad_k")
+        return out
+
+    # -- solver ---------------------------------------------------------
+    @staticmethod
+    def default_opts() -> SemSolveOpts:
+        o = SemSolveOpts()
+        lib().sem_solve_opts_default(ctypes.byref(o))
+        return o
+
+    def solve(self, b, x=None, raise_on_error=True, **kw):
+        """Solve R(h1 A(k) + h2 B)R^T x = R b; returns (x, stats dict, status).
+        Keyword options are the fields of sem_solve_opts (k as a tensor,
+        precond as "jacobi"/"pmg")."""
+        torch = _torch()
+        o = self.default_opts()
+        kk = kw.pop("k", None)
+        pre = kw.pop("precond", None)
+        if pre is not None:
+            o.precond = {"jacobi": SEM_PRECOND_JACOBI, "pmg": SEM_PRECOND_PMG}.get(pre, pre)
+        for name, val in kw.items():
+            if not hasattr(o, name):
+                raise TypeError(f"unknown solver option {name}")
+            setattr(o, name, val)
+        if kk is not None:
+            o.k = _dev_ptr(kk, torch.float64, self.n_local, "k").value
+        if x is None:
+            x = torch.zeros_like(b)
+            o.zero_guess = 1
+        st = SemSolveStats()
+        rc = lib().sem_pcg_solve(self._handle(), _dev_ptr(b, torch.float64, self.n_local, "b"),
+                                 _dev_ptr(x, torch.float64, self.n_local, "x"), ctypes.byref(o),
+                                 ctypes.byref(st), _stream())
+        if raise_on_error and rc not in (SEM_OK, SEM_ENOCONV):
+            _check(rc, "sem_pcg_solve")
+        return x, st.as_dict(), rc
+
+    # -- introspection ----------------------------------------------------
+    def info(self, level=0):
+        inf = SemInfo()
+        _check(lib().sem_info(self._handle(), level, ctypes.byref(inf)), "sem_info")
+        return inf.as_dict()
+
+    def maps(self, level=0):
+        torch = _torch()
+        inf = self.info(level)
+        perm = torch.empty(max(inf["n_shared_copies"], 1), dtype=torch.int32, device="cuda")
+        offs = torch.empty(inf["n_segments"] + 1, dtype=torch.int32, device="cuda")
+        _check(lib().sem_get_maps(self._handle(), level, ctypes.c_void_p(perm.data_ptr()),
+                                  ctypes.c_void_p(offs.data_ptr()), _stream()), "sem_get_maps")
+        return perm[: inf["n_shared_copies"]], offs
+
+    def geometry(self, level=0):
+        torch = _torch()
+        n = self.info(level)["n_local"]
+        G = torch.empty(6, n, dtype=torch.float64, device="cuda")
+        B = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(lib().sem_get_geometry(self._handle(), level, ctypes.c_void_p(G.data_ptr()),
+                                      ctypes.c_void_p(B.data_ptr()), _stream()), "sem_get_geometry")
+        return G, B
+
+    def weights(self, level=0):
+        torch = _torch()
+        n = self.info(level)["n_local"]
+        W = torch.empty(n, dtype=torch.float64, device="cuda")
+        g = torch.empty(n, dtype=torch.int64, device="cuda")
+        _check(lib().sem_get_weights(self._handle(), level, ctypes.c_void_p(W.data_ptr()),
+                                     ctypes.c_void_p(g.data_ptr()), _stream()), "sem_get_weights")
+        return W, g
