@@ -193,6 +193,8 @@ def main():
     ap.add_argument("--pcg-rhs", type=int, default=3)
     ap.add_argument("--coarse-tol", type=float, default=1e-2)
     ap.add_argument("--coarse-maxit", type=int, default=100)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain elementwise copy of this many MiB (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -249,6 +251,14 @@ def main():
             "algorithmic_bytes_per_launch": ax_bytes,
         },
     }
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.rand(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)  # reads n*8 bytes, writes n*8 bytes
+        torch.cuda.synchronize()
+        line["copy_probe"] = {"bytes_read": n * 8, "bytes_written": n * 8, "launches": 3}
     if not args.no_cpu:
         log(f"[bench] cpu baseline: oracle Ax + QQ^T, about {args.cpu_seconds} s")
         dt, reps = cpu_baseline(op["mesh"], args.cpu_seconds)
