@@ -96,6 +96,12 @@ static int build_level(Level &L, int N, int64_t E, const double *x, const double
 {
     L.gid = const_cast<int64_t *>(gid);
     L.dir = const_cast<uint8_t *>(dir);
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            L.n_cu = ncu;
+    }
     L.N = N;
     L.nq = N + 1;
     L.np = L.nq * L.nq * L.nq;
@@ -459,15 +465,14 @@ int sem_get_maps(sem_handle h, int level, int32_t *perm, int32_t *offs, void *st
     return SEM_OK;
 }
 
+// handle layout [E][np][6] -> caller layout [6][n_local]
 __global__ void unblock_G_kernel(int64_t nL, int np, const double *__restrict__ Gb, double *__restrict__ G)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 6 * nL) return;
     const int slot = (int)(t / nL);
     const int64_t q = t - slot * nL;
-    const int64_t e = q / np;
-    const int p = (int)(q - e * np);
-    G[t] = Gb[(e * 6 + slot) * np + p];
+    G[t] = Gb[q * 6 + slot];
 }
 
 int sem_get_geometry(sem_handle h, int level, double *G, double *B, void *stream)

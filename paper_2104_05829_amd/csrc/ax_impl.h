@@ -3,14 +3,20 @@
 //
 // Thread layout (the 2D-thread / 1D-register structure of Sec. 3.3): a thread
 // owns one (i,j) column of an element and keeps the k-line of u and of the
-// result in registers; u and the intermediate r/s-direction fluxes sit in LDS.
-// With (N+1)^2 <= 64 every element lives inside one 64-lane wavefront, so the
-// kernel needs no workgroup barrier: LDS traffic of one wave is ordered.
+// result in registers; u and the r/s-direction fluxes sit in LDS.  With
+// (N+1)^2 <= 64 every element lives inside one 64-lane wavefront, so LDS
+// traffic of an element is ordered without workgroup barriers and the
+// r-flux can overwrite u plane by plane (8.6 KiB of LDS per element at N=7).
 //   step 1: ur = D1 u, us = D2 u  (LDS rows), ut = D3 u (registers)
 //   step 2: (wr, ws, wt) = k G (ur, us, ut), G the symmetric 3x3 per point,
-//           G streamed coalesced from HBM (element-blocked [E][6][np])
+//           the six factors of a point contiguous ([E][np][6], 48 B, three
+//           16-byte loads per lane, each wavefront reading 3 KiB contiguous
+//           per plane)
 //   step 3: w = D1^T wr + D2^T ws (LDS) + D3^T wt (registers, accumulated
 //           while the k-planes are swept)
+// The grid is persistent (a few workgroups per CU, each sweeping elements
+// with a grid stride) and the next element's u is loaded while the current
+// one is computed.
 // Bytes per point (FP64 Poisson): u 8 + G 48 + w 8 = 64 (+8 for B, +8 for k).
 #pragma once
 #include "sem_internal.h"
@@ -39,6 +45,20 @@ __device__ inline void block_sync()
     }
 }
 
+// six geometric factors of one point, stored contiguously
+__device__ inline void load_g6(const double *p, double g[6])
+{
+    const double2 *q = reinterpret_cast<const double2 *>(p);
+    const double2 a = q[0], b = q[1], c = q[2];
+    g[0] = a.x; g[1] = a.y; g[2] = b.x; g[3] = b.y; g[4] = c.x; g[5] = c.y;
+}
+__device__ inline void load_g6(const float *p, float g[6])
+{
+    const float2 *q = reinterpret_cast<const float2 *>(p);
+    const float2 a = q[0], b = q[1], c = q[2];
+    g[0] = a.x; g[1] = a.y; g[2] = b.x; g[3] = b.y; g[4] = c.x; g[5] = c.y;
+}
+
 template <int NQ, typename T, bool HELM, bool VARK, bool DOT>
 __global__ void __launch_bounds__(AxShape<NQ>::THREADS)
 ax_kernel(int64_t E, const T *__restrict__ G, const T *__restrict__ B,
@@ -50,17 +70,16 @@ ax_kernel(int64_t E, const T *__restrict__ G, const T *__restrict__ B,
     using S = AxShape<NQ>;
     constexpr int TPE = S::TPE, EPB = S::EPB, LD = S::LD;
     constexpr int NP = NQ * NQ * NQ;
+    constexpr bool INPLACE = S::ONE_WAVE;
     __shared__ T su[EPB][NQ][NQ][LD];
-    __shared__ T sr[EPB][NQ][NQ][LD];
+    __shared__ T sr_[INPLACE ? 1 : EPB][NQ][NQ][LD];
     __shared__ T ss[EPB][NQ][NQ][LD];
 
     const int tid = threadIdx.x;
-    const int el = tid / TPE;
-    const int ij = tid - el * TPE;
+    const int el = (EPB == 1) ? 0 : tid / TPE;  // element slot within the block
+    const int ij = (EPB == 1) ? tid : tid - el * TPE;
     const int i = ij % NQ;
     const int j = ij / NQ;
-    const int64_t e = (int64_t)blockIdx.x * EPB + el;
-    const bool active = e < E;
 
     T Di[NQ], Dj[NQ], DTi[NQ], DTj[NQ];
 #pragma unroll
@@ -71,62 +90,90 @@ ax_kernel(int64_t E, const T *__restrict__ G, const T *__restrict__ B,
         DTj[l] = Dg[l * NQ + j];
     }
 
-    const int64_t base = (active ? e : 0) * NP + j * NQ + i;
-    T ru[NQ], rw[NQ];
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-        ru[k] = active ? u[base + k * TPE] : T(0);
-        su[el][k][j][i] = ru[k];
-        rw[k] = T(0);
-    }
-    block_sync<S::ONE_WAVE>();
-
-    const T *Ge = G + (active ? e : 0) * 6 * NP + j * NQ + i;
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-        T ur = 0, us = 0, ut = 0;
-#pragma unroll
-        for (int l = 0; l < NQ; ++l) {
-            ur += Di[l] * su[el][k][j][l];
-            us += Dj[l] * su[el][k][l][i];
-            ut += Dg[k * NQ + l] * ru[l];
-        }
-        const int off = k * TPE;
-        T g11 = Ge[0 * NP + off], g12 = Ge[1 * NP + off], g13 = Ge[2 * NP + off];
-        T g22 = Ge[3 * NP + off], g23 = Ge[4 * NP + off], g33 = Ge[5 * NP + off];
-        if constexpr (VARK) {
-            const T c = kc[base + off];
-            g11 *= c; g12 *= c; g13 *= c; g22 *= c; g23 *= c; g33 *= c;
-        }
-        const T wr = g11 * ur + g12 * us + g13 * ut;
-        const T ws = g12 * ur + g22 * us + g23 * ut;
-        const T wt = g13 * ur + g23 * us + g33 * ut;
-        sr[el][k][j][i] = wr;
-        ss[el][k][j][i] = ws;
-#pragma unroll
-        for (int m = 0; m < NQ; ++m) rw[m] += Dg[k * NQ + m] * wt;
-    }
-    block_sync<S::ONE_WAVE>();
-
     double dot = 0.0;
+    T rn[NQ];
+    int64_t g = blockIdx.x;  // element group: elements g*EPB .. g*EPB+EPB-1
+    {
+        const int64_t e0 = g * EPB + el;
+        if (e0 < E) {
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-        T acc = rw[k];
+            for (int k = 0; k < NQ; ++k) rn[k] = u[e0 * NP + ij + k * TPE];
+        } else {
 #pragma unroll
-        for (int l = 0; l < NQ; ++l) {
-            acc += DTi[l] * sr[el][k][j][l];
-            acc += DTj[l] * ss[el][k][l][i];
+            for (int k = 0; k < NQ; ++k) rn[k] = T(0);
         }
-        T out = h1 * acc;
-        if constexpr (HELM) out += h2 * B[base + k * TPE] * ru[k];
-        if (active) w[base + k * TPE] = out;
-        if constexpr (DOT) dot += (double)ru[k] * (double)out;
+    }
+    for (; g * EPB < E; g += gridDim.x) {
+        const int64_t e = g * EPB + el;
+        const bool active = e < E;
+        const int64_t base = (active ? e : 0) * NP + ij;
+        T ru[NQ], rw[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            ru[k] = rn[k];
+            su[el][k][j][i] = ru[k];
+            rw[k] = T(0);
+        }
+        {  // next element's u, loaded while this one is computed
+            const int64_t en = (g + gridDim.x) * EPB + el;
+            if (en < E) {
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) rn[k] = u[en * NP + ij + k * TPE];
+            }
+        }
+        block_sync<S::ONE_WAVE>();
+
+        const T *Ge = G + base * 6;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            T ur = 0, us = 0, ut = 0;
+#pragma unroll
+            for (int l = 0; l < NQ; ++l) {
+                ur += Di[l] * su[el][k][j][l];
+                us += Dj[l] * su[el][k][l][i];
+                ut += Dg[k * NQ + l] * ru[l];
+            }
+            T gg[6];
+            load_g6(Ge + k * TPE * 6, gg);
+            if constexpr (VARK) {
+                const T c = kc[base + k * TPE];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) gg[q] *= c;
+            }
+            const T wr = gg[0] * ur + gg[1] * us + gg[2] * ut;
+            const T ws = gg[1] * ur + gg[3] * us + gg[4] * ut;
+            const T wt = gg[2] * ur + gg[4] * us + gg[5] * ut;
+            if constexpr (INPLACE)
+                su[el][k][j][i] = wr;  // plane k of u is no longer read
+            else
+                sr_[el][k][j][i] = wr;
+            ss[el][k][j][i] = ws;
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) rw[m] += Dg[k * NQ + m] * wt;
+        }
+        block_sync<S::ONE_WAVE>();
+
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            T acc = rw[k];
+#pragma unroll
+            for (int l = 0; l < NQ; ++l) {
+                acc += DTi[l] * (INPLACE ? su[el][k][j][l] : sr_[el][k][j][l]);
+                acc += DTj[l] * ss[el][k][l][i];
+            }
+            T out = h1 * acc;
+            if constexpr (HELM) out += h2 * B[base + k * TPE] * ru[k];
+            if (active) w[base + k * TPE] = out;
+            if constexpr (DOT)
+                if (active) dot += (double)ru[k] * (double)out;
+        }
+        block_sync<S::ONE_WAVE>();  // LDS is rewritten by the next element
     }
 
     if constexpr (DOT) {
         // deterministic block sum: LDS slots, summed by thread 0 in order
         __shared__ double sdot[S::THREADS];
-        sdot[tid] = active ? dot : 0.0;
+        sdot[tid] = dot;
         __syncthreads();
         if (tid == 0) {
             double s = 0.0;
@@ -136,13 +183,18 @@ ax_kernel(int64_t E, const T *__restrict__ G, const T *__restrict__ B,
     }
 }
 
+// workgroups per CU of the persistent grid
+constexpr int kAxBlocksPerCU = 8;
+
 template <int NQ, typename T>
 static int ax_dispatch(const Level &L, const T *G, const T *B, const T *D, const T *u, T *w,
                        double h1, double h2, const T *k, double *partial, int64_t *nblocks,
                        hipStream_t s, const int *skip)
 {
     using S = AxShape<NQ>;
-    const int64_t nb = (L.E + S::EPB - 1) / S::EPB;
+    const int64_t groups = (L.E + S::EPB - 1) / S::EPB;
+    const int64_t cap = (int64_t)(L.n_cu > 0 ? L.n_cu : 256) * kAxBlocksPerCU;
+    const int64_t nb = groups < cap ? groups : cap;
     if (nblocks) *nblocks = nb;
     if (nb == 0) return SEM_OK;
     const bool helm = h2 != 0.0;

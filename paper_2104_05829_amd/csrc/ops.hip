@@ -9,13 +9,23 @@ namespace semx {
 // in ascending local index, the sum starts from 0 and adds them in that order,
 // then every copy receives it.  Unshared copies are never touched.
 // ---------------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2;
+// give XCD x the x-th contiguous chunk of segments so that neighbouring
+// segments (which share cache lines of the L-vector) meet in one L2.
+__device__ inline int64_t xcd_chunk_block(int64_t b, int64_t nb)
+{
+    const int64_t x = b % 8, q = b / 8;
+    const int64_t per = nb / 8, rem = nb % 8;
+    return x * per + (x < rem ? x : rem) + q;
+}
+
 template <typename T>
 __global__ void gs_kernel(int64_t nseg, const int32_t *__restrict__ perm,
                           const int32_t *__restrict__ offs, T *__restrict__ v,
                           const int *__restrict__ skip)
 {
     if (skip != nullptr && *skip != 0) return;
-    const int64_t sidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t sidx = xcd_chunk_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (sidx >= nseg) return;
     const int a = offs[sidx], b = offs[sidx + 1];
     T acc = T(0);
@@ -40,7 +50,7 @@ template int launch_gs<float>(const Level &, float *, hipStream_t, const int *);
 // Geometric factors (Sec. 2.3 eqs. (grad), (vBu), (gij)): one block per
 // element, one thread per point.  dx_p/dr_q = D_q x_p; J = det; dr/dx from the
 // adjugate; B = rho_i rho_j rho_k J; G_mm' = (sum_l dr_m/dx_l dr_m'/dx_l) B.
-// G is written element-blocked [E][6][np].  bad is set when J <= 0.
+// G is written point-interleaved [E][np][6].  bad is set when J <= 0.
 // ---------------------------------------------------------------------------
 __global__ void geometry_kernel(int64_t E, int nq, const double *__restrict__ x,
                                 const double *__restrict__ y, const double *__restrict__ z,
@@ -81,12 +91,12 @@ __global__ void geometry_kernel(int64_t E, int nq, const double *__restrict__ x,
         B[e * np + p] = w;
         // G_mm' = sum_a (C[m][a]/J)(C[m'][a]/J) rho J = sum_a C[m][a] C[m'][a] rho / J
         const double sc = rho[i] * rho[j] * rho[k] / J;
-        double *Ge = G + e * 6 * np + p;
+        double *Ge = G + (e * np + p) * 6;
         int slot = 0;
         for (int m = 0; m < 3; ++m)
             for (int mp = m; mp < 3; ++mp) {
                 const double g = C[m][0] * C[mp][0] + C[m][1] * C[mp][1] + C[m][2] * C[mp][2];
-                Ge[slot * np] = g * sc;
+                Ge[slot] = g * sc;
                 ++slot;
             }
     }
@@ -120,18 +130,18 @@ __global__ void diag_kernel(int64_t nL, int nq, const double *__restrict__ G,
     const int64_t e = q / np;
     const int p = (int)(q - e * np);
     const int i = p % nq, j = (p / nq) % nq, k = p / (nq * nq);
-    const double *Ge = G + e * 6 * np;
+    const double *Ge = G + e * np * 6;  // [np][6]
     const double *ke = kc ? kc + e * np : nullptr;
     double s = 0.0;
     for (int l = 0; l < nq; ++l) {
         const int pi = l + nq * (j + nq * k), pj = i + nq * (l + nq * k), pk = i + nq * (j + nq * l);
-        s += D[l * nq + i] * D[l * nq + i] * Ge[0 * np + pi] * (ke ? ke[pi] : 1.0);
-        s += D[l * nq + j] * D[l * nq + j] * Ge[3 * np + pj] * (ke ? ke[pj] : 1.0);
-        s += D[l * nq + k] * D[l * nq + k] * Ge[5 * np + pk] * (ke ? ke[pk] : 1.0);
+        s += D[l * nq + i] * D[l * nq + i] * Ge[pi * 6 + 0] * (ke ? ke[pi] : 1.0);
+        s += D[l * nq + j] * D[l * nq + j] * Ge[pj * 6 + 3] * (ke ? ke[pj] : 1.0);
+        s += D[l * nq + k] * D[l * nq + k] * Ge[pk * 6 + 5] * (ke ? ke[pk] : 1.0);
     }
     const double c = ke ? ke[p] : 1.0;
     const double di = D[i * nq + i], dj = D[j * nq + j], dk = D[k * nq + k];
-    s += 2.0 * c * (di * dj * Ge[1 * np + p] + di * dk * Ge[2 * np + p] + dj * dk * Ge[4 * np + p]);
+    s += 2.0 * c * (di * dj * Ge[p * 6 + 1] + di * dk * Ge[p * 6 + 2] + dj * dk * Ge[p * 6 + 4]);
     double v = h1 * s;
     if (h2 != 0.0) v += h2 * B[q];
     d[q] = v;
@@ -175,9 +185,8 @@ __global__ void grad_k_kernel(int64_t nL, int nq, const double *__restrict__ G,
         c1 += D[j * nq + l] * ue[pj];
         c2 += D[k * nq + l] * ue[pk];
     }
-    const double *Ge = G + e * 6 * np + p;
-    const double g11 = Ge[0], g12 = Ge[np], g13 = Ge[2 * np], g22 = Ge[3 * np], g23 = Ge[4 * np],
-                 g33 = Ge[5 * np];
+    const double *Ge = G + (e * np + p) * 6;
+    const double g11 = Ge[0], g12 = Ge[1], g13 = Ge[2], g22 = Ge[3], g23 = Ge[4], g33 = Ge[5];
     const double s = a0 * (g11 * c0 + g12 * c1 + g13 * c2) + a1 * (g12 * c0 + g22 * c1 + g23 * c2)
                    + a2 * (g13 * c0 + g23 * c1 + g33 * c2);
     gk[q] = -h1 * s;

@@ -52,9 +52,10 @@ struct KrylovScalars {
 // One polynomial order of the discretisation on the handle's mesh.
 struct Level {
     int N = 0, nq = 0, np = 0;
+    int n_cu = 0;  // compute units of the device (persistent grid size)
     int64_t E = 0, nL = 0;
     int64_t n_unique = 0, ncopies = 0, nseg = 0;
-    // geometry: G element-blocked [E][6][np] (G11,G12,G13,G22,G23,G33), B [nL]
+    // geometry: G point-interleaved [E][np][6] (G11,G12,G13,G22,G23,G33), B [nL]
     double *G = nullptr, *B = nullptr;
     float *G32 = nullptr, *B32 = nullptr;
     double *W = nullptr;   // counting weight, 0 on Dirichlet copies
