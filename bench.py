@@ -160,6 +160,62 @@ def bench_pcg(args, torch, sem_mod, inputs):
     return out
 
 
+def bench_large(args, torch, sem_mod, inputs):
+    """64x64x32 elements on [0,2]x[0,2]x[0,1] (cubic elements of side 1/32),
+    cyclic perturbation, N=7 (67,108,864 local points), Poisson (h2 = 0),
+    homogeneous Dirichlet, f ~ N(0,1) per node (rng(50)); both solvers to a
+    relative residual of 1e-8.  Also times the FP64 element operator alone."""
+    N = 7
+    t0 = time.perf_counter()
+    mesh = sem_mod.box_mesh(64, 64, 32, N, L=(2.0, 2.0, 1.0), deform="cyclic", amp=0.05,
+                            bc="dirichlet")
+    t_mesh = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    s = sem_mod.Sem(mesh, levels=(7, 3, 1))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    f = torch.tensor(inputs.gaussian_per_node(mesh.gid, 50), device="cuda")
+    del mesh
+    b = s.rhs(f)
+    del f
+    inf = s.info()
+    nL = inf["n_local"]
+    # operator alone
+    w = torch.empty_like(b)
+    for _ in range(3):
+        s.ax(b, w)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(10):
+        s.ax(b, w)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_ax = ev0.elapsed_time(ev1) / 10
+    del w
+    out = {"workload": "64x64x32 deformed box on [0,2]^2x[0,1], N=7, Poisson, 1 RHS, "
+                       "relative residual 1e-8",
+           "n_unique": inf["n_unique"], "n_local": nL, "mesh_s": round(t_mesh, 2),
+           "setup_s": round(t_setup, 3), "ms_ax_fp64": round(ms_ax, 4),
+           "ax_fp64_GBps": round(AX_BYTES_PER_POINT * nL / (ms_ax * 1e-3) / 1e9, 1)}
+    for pre in ("pmg", "jacobi"):
+        s.solve(b, tol=1e-8, precond=pre, maxit=1)  # builds and caches the preconditioner
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st, rc = s.solve(b, tol=1e-8, precond=pre, maxit=50000, coarse_tol=args.coarse_tol,
+                            coarse_maxit=args.coarse_maxit)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[pre] = {"ms": round(dt * 1e3, 2), "iters": st["iters"],
+                    "true_rel_res": float(f"{st['true_rel_res']:.3e}"), "status": rc}
+        if pre == "pmg":
+            out[pre]["coarse_iters"] = st["coarse_iters"]
+        del x
+    out["speedup_pmg_vs_jacobi"] = round(out["jacobi"]["ms"] / out["pmg"]["ms"], 3)
+    s.free()
+    return out
+
+
 def cpu_baseline(mesh, seconds):
     """The oracle's Ax + QQ^T on the full 16^3 N=7 mesh, repeated until
     about `seconds` of CPU time; single-threaded C (no OpenMP)."""
@@ -193,6 +249,8 @@ def main():
     ap.add_argument("--pcg-rhs", type=int, default=3)
     ap.add_argument("--coarse-tol", type=float, default=1e-2)
     ap.add_argument("--coarse-maxit", type=int, default=100)
+    ap.add_argument("--large", action="store_true",
+                    help="also time the 64x64x32 Poisson case (PMG-FCG vs Jacobi-PCG to 1e-8)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (counter scaling)")
     args = ap.parse_args()
@@ -271,6 +329,9 @@ def main():
     if not args.no_pcg:
         log("[bench] pcg: 32^3 Helmholtz, FCG+FP32 p-MG vs FP64 Jacobi-PCG to 1e-8")
         line["pcg"] = bench_pcg(args, torch, sem_mod, inputs)
+    if args.large:
+        log("[bench] large: 64x64x32 Poisson, FCG+FP32 p-MG vs FP64 Jacobi-PCG to 1e-8")
+        line["pcg_large"] = bench_large(args, torch, sem_mod, inputs)
     print(json.dumps(line), flush=True)
 
 

@@ -193,6 +193,28 @@ SEM_API int sem_pcg_solve(sem_handle h, const double *b, double *x, const sem_so
 SEM_API int sem_grad_k(sem_handle h, const double *u, const double *lam, double h1, double *gk,
                void *stream);
 
+/*
+ * Load vector of the weak form (Sec. 2.3: b_i = (phi_i, f) by GLL quadrature,
+ * eq. (vBu)), assembled and restricted:  b = R QQ^T (B_L o f_L), i.e. Dirichlet
+ * copies of b are zero.  f, b: device L-vectors (may alias).
+ */
+SEM_API int sem_rhs(sem_handle h, const double *f, double *b, void *stream);
+
+/*
+ * Hand-written adjoint of the solve u = A(k)^{-1} R QQ^T(B f) for a loss L(u)
+ * with g = dL/du_L (per copy):
+ *   lam    = A(k)^{-1} R QQ^T g      (one more solve; A is symmetric)
+ *   grad_f = B_L o lam              (dL/df_L per copy)
+ *   grad_k = -h1 (D lam)^T G (D u)  (dL/dk_L per copy, as sem_grad_k; NULL to skip)
+ * u is the forward solution (replicated L-vector).  opts gives h1, h2, k and
+ * the tolerance of the adjoint solve (Jacobi-preconditioned; PMG if k is NULL
+ * and the handle has levels).  lam is output storage; grad_f may be NULL.
+ * Returns the adjoint solve's status.  Synchronises `stream`.
+ */
+SEM_API int sem_adjoint(sem_handle h, const double *u, const double *g, const sem_solve_opts *opts,
+                        double *lam, double *grad_f, double *grad_k, sem_solve_stats *stats,
+                        void *stream);
+
 /* Sizes of a level (0 = fine). */
 typedef struct {
     int N;

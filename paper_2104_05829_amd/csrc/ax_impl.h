@@ -183,8 +183,7 @@ ax_kernel(int64_t E, const T *__restrict__ G, const T *__restrict__ B,
     }
 }
 
-// workgroups per CU of the persistent grid
-constexpr int kAxBlocksPerCU = 8;
+constexpr int kAxBlocksPerCU = kAxBlocksPerCUHost;
 
 template <int NQ, typename T>
 static int ax_dispatch(const Level &L, const T *G, const T *B, const T *D, const T *u, T *w,

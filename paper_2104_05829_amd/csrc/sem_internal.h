@@ -30,6 +30,9 @@ void set_error(const char *fmt, ...);
     } while (0)
 
 constexpr int kMaxN = 15;
+// workgroups per CU of the persistent element-operator grid (the operator's
+// partial-sum buffer holds one value per workgroup)
+constexpr int kAxBlocksPerCUHost = 8;
 constexpr int kMaxLevels = 4;
 
 // Device scalars of one Krylov solve (kept on the device between kernels).
@@ -43,6 +46,8 @@ struct KrylovScalars {
     double rr;      // (r, r)_W
     double bb;      // (b, b)_W
     double tol2;    // tol^2 (b, b)_W
+    double rz2[2];  // (r, z)_W by iteration parity (written by one block while
+                    // the other slot is read by all blocks of the same kernel)
     int iters;
     int done;       // 1 once converged or failed; later kernels become no-ops
     int status;     // SEM_OK / SEM_EBREAKDOWN
@@ -63,6 +68,7 @@ struct Level {
     int64_t *gid = nullptr;
     uint8_t *dir = nullptr;
     int32_t *perm = nullptr, *offs = nullptr;
+    int32_t *segid = nullptr;  // per copy: segment of its node in perm, -1 if unshared
     double *D = nullptr;   // Dh [nq][nq] (row = point)
     float *D32 = nullptr;
     // interpolation from the next coarser level's nodes to this level's
@@ -79,9 +85,12 @@ struct Workspace {
     int64_t nL = 0;
     // FP64 outer vectors
     double *r = nullptr, *p = nullptr, *w = nullptr, *z = nullptr;
+    double *aux = nullptr;  // adjoint right-hand side
     // reduction partials and scalars
-    double *partial = nullptr;
+    double *partial = nullptr;     // vector-kernel partial sums
     int64_t n_partial = 0;
+    double *partial_ax = nullptr;  // operator-kernel partial sums of (p, A_L p)
+    int64_t n_partial_ax = 0;
     KrylovScalars *sc = nullptr;      // outer
     KrylovScalars *sc_c = nullptr;    // coarse
     KrylovScalars *host_sc = nullptr; // pinned mirror

@@ -120,22 +120,6 @@ __global__ void dot_kernel(int64_t n, const double *__restrict__ W, const double
     block_sum_store<1>(s, partial);
 }
 
-// two dots with a common left factor: (W z a, W z b)
-__global__ void dot2_kernel(int64_t n, const KrylovScalars *sc, const double *__restrict__ W,
-                            const double *__restrict__ zv, const double *__restrict__ a,
-                            const double *__restrict__ b, double *__restrict__ partial)
-{
-    if (sc && sc->done) return;
-    double s[2] = {0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const double wz = W[i] * zv[i];
-        s[0] += wz * a[i];
-        s[1] += wz * b[i];
-    }
-    block_sum_store<2>(s, partial);
-}
-
 // ---------------------------------------------------------------- Jacobi-PCG
 // r = b - Ax (Ax may be null: x = 0), p = Dinv r; partials (W r p, W r r, W b b)
 __global__ void pcg_init_kernel(int64_t n, const double *__restrict__ b, const double *__restrict__ Ax,
@@ -166,6 +150,8 @@ __global__ void fin_init_kernel(const double *partial, int64_t nb, KrylovScalars
     if (threadIdx.x == 0) {
         sc->rz = res[0];
         sc->rz_old = res[0];
+        sc->rz2[0] = res[0];
+        sc->rz2[1] = res[0];
         sc->rr = res[1];
         sc->bb = res[2];
         sc->tol2 = tol * tol * res[2];
@@ -179,36 +165,63 @@ __global__ void fin_init_kernel(const double *partial, int64_t nb, KrylovScalars
     }
 }
 
-__global__ void fin_alpha_kernel(const double *partial, int64_t nb, KrylovScalars *sc)
+// ------------------------------------------------- fused Krylov iterations
+// QQ^T value of copy l.  With segid == nullptr, w is already assembled (a
+// gs_kernel pass ran before); otherwise the sum over the copies of its node is
+// taken on the fly in the canonical order, starting from 0 (bit-identical to
+// gs_kernel's).  The on-the-fly form trades the gs pass for dependent
+// scattered loads and is only worth it for tiny levels.
+template <typename T>
+__device__ inline T assembled_value(const T *__restrict__ w, int64_t l,
+                                    const int32_t *__restrict__ segid,
+                                    const int32_t *__restrict__ perm,
+                                    const int32_t *__restrict__ offs)
+{
+    if (segid == nullptr) return w[l];
+    const int sg = segid[l];
+    if (sg < 0) return w[l];
+    const int a = offs[sg], b = offs[sg + 1];
+    T acc = T(0);
+    for (int o = a; o < b; ++o) acc += w[perm[o]];
+    return acc;
+}
+
+// Jacobi-PCG update.  Every block sums the operator kernel's partials of
+// (p, A_L p) in the same fixed order, so all blocks hold the same alpha;
+// x += alpha p; r -= alpha QQ^T(A_L p); partials (W r Dinv r, W r r).
+// rz2[parity] is the current (r, z).
+__global__ void pcg_update_fused_kernel(int64_t n, KrylovScalars *sc, int parity,
+                                        const double *__restrict__ pax, int64_t nbax,
+                                        const double *__restrict__ p, const double *__restrict__ w,
+                                        const int32_t *__restrict__ segid,
+                                        const int32_t *__restrict__ perm,
+                                        const int32_t *__restrict__ offs,
+                                        const double *__restrict__ Dinv,
+                                        const double *__restrict__ W, double *__restrict__ x,
+                                        double *__restrict__ r, double *__restrict__ partial)
 {
     if (sc->done) return;
     double res[1];
-    sum_partials<1>(partial, nb, res);
-    if (threadIdx.x == 0) {
-        const double pw = res[0];
-        sc->pw = pw;
-        if (!(pw > 0.0) || !isfinite(pw)) {
+    sum_partials<1>(pax, nbax, res);
+    const double pw = res[0];
+    if (!(pw > 0.0) || !isfinite(pw)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->pw = pw;
             sc->status = SEM_EBREAKDOWN;
             sc->done = 1;
-            return;
         }
-        sc->alpha = sc->rz / pw;
+        return;
     }
-}
-
-// x += a p; r -= a w; z = Dinv r (not stored); partials (W r z, W r r)
-__global__ void pcg_update_kernel(int64_t n, const KrylovScalars *sc, const double *__restrict__ p,
-                                  const double *__restrict__ w, const double *__restrict__ Dinv,
-                                  const double *__restrict__ W, double *__restrict__ x,
-                                  double *__restrict__ r, double *__restrict__ partial)
-{
-    if (sc->done) return;
-    const double a = sc->alpha;
+    const double a = sc->rz2[parity] / pw;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pw = pw;
+        sc->alpha = a;
+    }
     double s[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         x[i] += a * p[i];
-        const double ri = r[i] - a * w[i];
+        const double ri = r[i] - a * assembled_value(w, i, segid, perm, offs);
         r[i] = ri;
         const double wr = W[i] * ri;
         s[0] += wr * Dinv[i] * ri;
@@ -217,59 +230,151 @@ __global__ void pcg_update_kernel(int64_t n, const KrylovScalars *sc, const doub
     block_sum_store<2>(s, partial);
 }
 
-__global__ void fin_beta_kernel(const double *partial, int64_t nb, KrylovScalars *sc)
+// Jacobi-PCG direction update with beta and the convergence decision taken
+// by every block from the update's partials (identical in all blocks);
+// block 0 records them.  `iter` is the 1-based number of this iteration.
+__global__ void pcg_p_fused_kernel(int64_t n, KrylovScalars *sc, int parity, int iter,
+                                   const double *__restrict__ pu, int64_t nbu,
+                                   const double *__restrict__ Dinv, const double *__restrict__ r,
+                                   double *__restrict__ p)
 {
     if (sc->done) return;
     double res[2];
-    sum_partials<2>(partial, nb, res);
-    if (threadIdx.x == 0) {
-        const double rz = res[0], rr = res[1];
-        sc->iters += 1;
+    sum_partials<2>(pu, nbu, res);
+    const double rz = res[0], rr = res[1];
+    const bool bad = !isfinite(rz) || !isfinite(rr);
+    const bool stop = bad || rr <= sc->tol2 || iter >= sc->maxit;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->iters = iter;
         sc->rr = rr;
-        if (!isfinite(rz) || !isfinite(rr)) {
-            sc->status = SEM_EBREAKDOWN;
-            sc->done = 1;
-            return;
-        }
-        if (rr <= sc->tol2 || sc->iters >= sc->maxit) {
-            sc->done = 1;
-            return;
-        }
-        sc->beta = rz / sc->rz;
         sc->rz = rz;
+        sc->rz2[parity ^ 1] = rz;
+        if (bad) sc->status = SEM_EBREAKDOWN;
+        if (stop) sc->done = 1;
     }
-}
-
-__global__ void pcg_p_kernel(int64_t n, const KrylovScalars *sc, const double *__restrict__ Dinv,
-                             const double *__restrict__ r, double *__restrict__ p)
-{
-    if (sc->done) return;
-    const double be = sc->beta;
+    if (stop) return;
+    const double be = rz / sc->rz2[parity];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = Dinv[i] * r[i] + be * p[i];
 }
 
-// ------------------------------------------------------------- flexible CG
-// x += a p; r -= a w; partial (W r r)
-__global__ void fcg_update_kernel(int64_t n, const KrylovScalars *sc, const double *__restrict__ p,
-                                  const double *__restrict__ w, const double *__restrict__ W,
-                                  double *__restrict__ x, double *__restrict__ r,
-                                  double *__restrict__ partial)
+// flexible-CG update: alpha from the operator partials, x += alpha p,
+// r -= alpha QQ^T(A_L p); partial (W r r)
+__global__ void fcg_update_fused_kernel(int64_t n, KrylovScalars *sc, int parity,
+                                        const double *__restrict__ pax, int64_t nbax,
+                                        const double *__restrict__ p, const double *__restrict__ w,
+                                        const int32_t *__restrict__ segid,
+                                        const int32_t *__restrict__ perm,
+                                        const int32_t *__restrict__ offs,
+                                        const double *__restrict__ W, double *__restrict__ x,
+                                        double *__restrict__ r, double *__restrict__ partial)
 {
     if (sc->done) return;
-    const double a = sc->alpha;
+    double res[1];
+    sum_partials<1>(pax, nbax, res);
+    const double pw = res[0];
+    if (!(pw > 0.0) || !isfinite(pw)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->pw = pw;
+            sc->status = SEM_EBREAKDOWN;
+            sc->done = 1;
+        }
+        return;
+    }
+    const double a = sc->rz2[parity] / pw;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pw = pw;
+        sc->alpha = a;
+    }
     double s[1] = {0.0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         x[i] += a * p[i];
-        const double ri = r[i] - a * w[i];
+        const double ri = r[i] - a * assembled_value(w, i, segid, perm, offs);
         r[i] = ri;
         s[0] += W[i] * ri * ri;
     }
     block_sum_store<1>(s, partial);
 }
 
+// (z, w)_W and (z, r)_W for assembled w
+__global__ void dot_zw_kernel(int64_t n, const KrylovScalars *sc, const double *__restrict__ W,
+                              const double *__restrict__ z, const double *__restrict__ wa,
+                              const double *__restrict__ r, double *__restrict__ partial)
+{
+    if (sc->done) return;
+    double s[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double wz = W[i] * z[i];
+        s[0] += wz * wa[i];
+        s[1] += wz * r[i];
+    }
+    block_sum_store<2>(s, partial);
+}
+
+// Polak-Ribiere direction update, beta = (z_new, r_new - r_old) / (z_old, r_old)
+// = -alpha (z_new, A p) / rz_old (r_new - r_old = -alpha A p), taken by every
+// block from the partials of dot_zw_kernel; first = 1 gives p = z.
+__global__ void fcg_p_fused_kernel(int64_t n, KrylovScalars *sc, int parity,
+                                   const double *__restrict__ pz, int64_t nbz,
+                                   const double *__restrict__ z, double *__restrict__ p, int first)
+{
+    if (sc->done) return;
+    double res[2];
+    sum_partials<2>(pz, nbz, res);
+    const double zw = res[0], zr = res[1];
+    const double be = first ? 0.0 : -sc->alpha * zw / sc->rz2[parity];
+    const bool bad = !isfinite(be) || !isfinite(zr);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->zw = zw;
+        sc->beta = be;
+        sc->rz = zr;
+        sc->rz2[parity ^ 1] = zr;
+        if (bad) {
+            sc->status = SEM_EBREAKDOWN;
+            sc->done = 1;
+        }
+    }
+    if (bad) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + be * p[i];
+}
+
+// Chebyshev step with QQ^T of the operator output taken on the fly:
+// res = r - QQ^T t (t = A_L x, or absent when x = 0),
+// d = c1 d + c2 Dinv res, x += d (x = d when `init`)
+__global__ void cheb_fused_kernel(int64_t n, const float *__restrict__ r, const float *__restrict__ t,
+                                  const int32_t *__restrict__ segid, const int32_t *__restrict__ perm,
+                                  const int32_t *__restrict__ offs, const float *__restrict__ Dinv,
+                                  float *__restrict__ d, float *__restrict__ x, float c1, float c2,
+                                  int init)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float res = t ? r[i] - assembled_value(t, i, segid, perm, offs) : r[i];
+        const float di = (init ? 0.0f : c1 * d[i]) + c2 * Dinv[i] * res;
+        d[i] = di;
+        x[i] = init ? di : x[i] + di;
+    }
+}
+
+// s = W (r - QQ^T t)
+__global__ void wresid_fused_kernel(int64_t n, const float *__restrict__ W,
+                                    const float *__restrict__ r, const float *__restrict__ t,
+                                    const int32_t *__restrict__ segid,
+                                    const int32_t *__restrict__ perm,
+                                    const int32_t *__restrict__ offs, float *__restrict__ s)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        s[i] = W[i] * (r[i] - assembled_value(t, i, segid, perm, offs));
+}
+
+// flexible CG convergence decision after the update (one block): iteration
+// count, (r, r)_W, done
 __global__ void fin_conv_kernel(const double *partial, int64_t nb, KrylovScalars *sc)
 {
     if (sc->done) return;
@@ -287,76 +392,23 @@ __global__ void fin_conv_kernel(const double *partial, int64_t nb, KrylovScalars
     }
 }
 
-// rz = (z, r) at start
-__global__ void fin_rz_kernel(const double *partial, int64_t nb, KrylovScalars *sc)
-{
-    if (sc->done) return;
-    double res[2];
-    sum_partials<2>(partial, nb, res);
-    if (threadIdx.x == 0) sc->rz = res[1];
-}
-
-// Polak-Ribiere: beta = (z_new, r_new - r_old) / (z_old, r_old)
-//              = -alpha (z_new, w) / rz_old,  with r_new - r_old = -alpha w
-__global__ void fin_beta_fcg_kernel(const double *partial, int64_t nb, KrylovScalars *sc)
-{
-    if (sc->done) return;
-    double res[2];
-    sum_partials<2>(partial, nb, res);
-    if (threadIdx.x == 0) {
-        const double zw = res[0], zr = res[1];
-        sc->zw = zw;
-        sc->beta = -sc->alpha * zw / sc->rz;
-        sc->rz_old = sc->rz;
-        sc->rz = zr;
-        if (!isfinite(sc->beta) || !isfinite(zr)) {
-            sc->status = SEM_EBREAKDOWN;
-            sc->done = 1;
-        }
-    }
-}
-
-__global__ void fcg_p_kernel(int64_t n, const KrylovScalars *sc, const double *__restrict__ z,
-                             double *__restrict__ p, int first)
-{
-    if (sc->done) return;
-    const double be = first ? 0.0 : sc->beta;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = z[i] + be * p[i];
-}
-
-// ----------------------------------------------------------- FP32 smoothing
-// Chebyshev step: res = r - t (t = A x, or absent when x = 0),
-// d = c1 d + c2 Dinv res, x += d  (x = d when `init`)
-__global__ void cheb_kernel(int64_t n, const float *__restrict__ r, const float *__restrict__ t,
-                            const float *__restrict__ Dinv, float *__restrict__ d,
-                            float *__restrict__ x, float c1, float c2, int init)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const float res = t ? r[i] - t[i] : r[i];
-        const float di = (init ? 0.0f : c1 * d[i]) + c2 * Dinv[i] * res;
-        d[i] = di;
-        x[i] = init ? di : x[i] + di;
-    }
-}
-
-// s = W (r - t)
-__global__ void wresid_kernel(int64_t n, const float *__restrict__ W, const float *__restrict__ r,
-                              const float *__restrict__ t, float *__restrict__ s)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        s[i] = W[i] * (r[i] - t[i]);
-}
-
+// y += a (prolongation added to the smoothed iterate)
 template <typename T>
 __global__ void add_kernel(int64_t n, const T *__restrict__ a, T *__restrict__ y)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         y[i] += a[i];
+}
+
+// ---------------------------------------------------------- load / adjoint
+// y = B o x (mass-weighted copy)
+__global__ void mass_kernel(int64_t n, const double *__restrict__ B, const double *__restrict__ x,
+                            double *__restrict__ y)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = B[i] * x[i];
 }
 
 // ----------------------------------------------------------------- Lanczos
@@ -410,7 +462,8 @@ __global__ void axpby_kernel(int64_t n, const double *__restrict__ x, double a, 
 void free_workspace(sem_handle h)
 {
     Workspace &w = h->ws;
-    void *ptrs[] = {w.r, w.p, w.w, w.z, w.partial, w.sc, w.sc_c, w.c_r, w.c_p, w.c_w};
+    void *ptrs[] = {w.r, w.p, w.w, w.z, w.aux, w.partial, w.partial_ax, w.sc, w.sc_c, w.c_r,
+                    w.c_p, w.c_w};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (int l = 0; l < kMaxLevels; ++l) {
@@ -439,10 +492,12 @@ static int ensure_workspace(sem_handle h, bool pmg)
         SEM_HIP(hipMalloc(&w.p, sizeof(double) * F.nL));
         SEM_HIP(hipMalloc(&w.w, sizeof(double) * F.nL));
         SEM_HIP(hipMalloc(&w.z, sizeof(double) * F.nL));
-        // largest partial record set: one per Ax block (E at N >= 7) or
-        // kMaxRedBlocks records of 3
-        w.n_partial = std::max<int64_t>(F.E + 64, 3 * kMaxRedBlocks);
+        // vector-kernel partials: at most kMaxRedBlocks records of 3; operator
+        // partials: one per workgroup of the persistent operator grid
+        w.n_partial = 3 * kMaxRedBlocks;
         SEM_HIP(hipMalloc(&w.partial, sizeof(double) * w.n_partial));
+        w.n_partial_ax = (int64_t)(F.n_cu > 0 ? F.n_cu : 256) * kAxBlocksPerCUHost + 64;
+        SEM_HIP(hipMalloc(&w.partial_ax, sizeof(double) * w.n_partial_ax));
         SEM_HIP(hipMalloc(&w.sc, sizeof(KrylovScalars)));
         SEM_HIP(hipMalloc(&w.sc_c, sizeof(KrylovScalars)));
         SEM_HIP(hipHostMalloc((void **)&w.host_sc, 2 * sizeof(KrylovScalars), hipHostMallocDefault));
@@ -580,12 +635,12 @@ struct ChebCoef {
     double theta, delta;
 };
 
-// restricted FP32 operator on a smoother level: t = mask(QQ^T(A_L x))
+// FP32 operator on a smoother level: t = QQ^T A_L x (Dirichlet copies of t are
+// ignored by the consumers, whose Dinv and W vanish there)
 static int apply_f32(const Level &L, const float *x, float *t, double h1, double h2, hipStream_t s)
 {
     SEM_TRY(launch_ax<float>(L, L.G32, L.B32, L.D32, x, t, h1, h2, nullptr, nullptr, nullptr, s));
-    SEM_TRY(launch_gs<float>(L, t, s));
-    return SEM_OK;
+    return launch_gs<float>(L, t, s);
 }
 
 // Chebyshev-accelerated Jacobi (Saad, Iterative Methods, Alg. 12.1, applied to
@@ -600,18 +655,18 @@ static int chebyshev(const Level &L, int l, sem_handle h, const float *r, float 
     const double sigma = theta / delta;
     double rho_prev = 1.0 / sigma;
     if (zero) {
-        LAUNCH_V(cheb_kernel, n, s, n, r, (const float *)nullptr, L.Dinv32, d, x, 0.0f,
-                 (float)(1.0 / theta), 1);
+        LAUNCH_V(cheb_fused_kernel, n, s, n, r, (const float *)nullptr, (const int32_t *)nullptr, L.perm, L.offs,
+                 L.Dinv32, d, x, 0.0f, (float)(1.0 / theta), 1);
     } else {
         SEM_TRY(apply_f32(L, x, t, h1, h2, s));
-        LAUNCH_V(cheb_kernel, n, s, n, r, (const float *)t, L.Dinv32, d, x, 0.0f,
-                 (float)(1.0 / theta), 0);
+        LAUNCH_V(cheb_fused_kernel, n, s, n, r, (const float *)t, (const int32_t *)nullptr, L.perm, L.offs,
+                 L.Dinv32, d, x, 0.0f, (float)(1.0 / theta), 0);
     }
     for (int k = 1; k < deg; ++k) {
         const double rho = 1.0 / (2.0 * sigma - rho_prev);
         SEM_TRY(apply_f32(L, x, t, h1, h2, s));
-        LAUNCH_V(cheb_kernel, n, s, n, r, (const float *)t, L.Dinv32, d, x, (float)(rho * rho_prev),
-                 (float)(2.0 * rho / delta), 0);
+        LAUNCH_V(cheb_fused_kernel, n, s, n, r, (const float *)t, (const int32_t *)nullptr, L.perm, L.offs,
+                 L.Dinv32, d, x, (float)(rho * rho_prev), (float)(2.0 * rho / delta), 0);
         rho_prev = rho;
     }
     return SEM_OK;
@@ -622,21 +677,27 @@ struct SolveCfg {
     int maxit, check_every, deg, coarse_maxit;
 };
 
-// enqueue `iters` Jacobi-PCG iterations on level L (vectors r, p, w, x; scalars sc)
+// enqueue Jacobi-PCG iterations first_iter .. first_iter+iters-1 (1-based)
+// on level L: operator with fused (p, A_L p), QQ^T, update with alpha, and
+// direction update with beta and the convergence decision -- four kernels per
+// iteration, no single-block reduction kernels
 static int pcg_iterations(const Level &L, const double *k, double h1, double h2, double *x,
-                          double *r, double *p, double *w, double *partial, KrylovScalars *sc,
-                          int iters, hipStream_t s)
+                          double *r, double *p, double *w, double *pax, double *partial,
+                          KrylovScalars *sc, int first_iter, int iters, hipStream_t s)
 {
     const int64_t n = L.nL;
     const int nbv = red_grid(n);
     for (int c = 0; c < iters; ++c) {
+        const int it = first_iter + c;
+        const int parity = (it - 1) & 1;
         int64_t nbax = 0;
-        SEM_TRY(launch_ax<double>(L, L.G, L.B, L.D, p, w, h1, h2, k, partial, &nbax, s, &sc->done));
+        SEM_TRY(launch_ax<double>(L, L.G, L.B, L.D, p, w, h1, h2, k, pax, &nbax, s, &sc->done));
         SEM_TRY(launch_gs<double>(L, w, s, &sc->done));
-        LAUNCH_1(fin_alpha_kernel, s, partial, nbax, sc);
-        LAUNCH_V(pcg_update_kernel, n, s, n, sc, p, w, L.Dinv, L.W, x, r, partial);
-        LAUNCH_1(fin_beta_kernel, s, partial, (int64_t)nbv, sc);
-        LAUNCH_V(pcg_p_kernel, n, s, n, sc, L.Dinv, r, p);
+        LAUNCH_V(pcg_update_fused_kernel, n, s, n, sc, parity, (const double *)pax, nbax,
+                 (const double *)p, (const double *)w, (const int32_t *)nullptr, L.perm, L.offs,
+                 L.Dinv, L.W, x, r, partial);
+        LAUNCH_V(pcg_p_fused_kernel, n, s, n, sc, parity, it, (const double *)partial,
+                 (int64_t)nbv, L.Dinv, (const double *)r, p);
     }
     return SEM_OK;
 }
@@ -672,8 +733,8 @@ static int vcycle(sem_handle h, int l, const SolveCfg &cfg, hipStream_t s)
         double *b = (double *)w.mg_r[l], *x = (double *)w.mg_x[l];
         SEM_TRY(pcg_start(L, nullptr, cfg.h1, cfg.h2, b, x, true, w.c_r, w.c_p, w.c_w, w.partial,
                           w.sc_c, cfg.coarse_tol, cfg.coarse_maxit, s));
-        SEM_TRY(pcg_iterations(L, nullptr, cfg.h1, cfg.h2, x, w.c_r, w.c_p, w.c_w, w.partial,
-                               w.sc_c, cfg.coarse_maxit, s));
+        SEM_TRY(pcg_iterations(L, nullptr, cfg.h1, cfg.h2, x, w.c_r, w.c_p, w.c_w, w.partial_ax,
+                               w.partial, w.sc_c, 1, cfg.coarse_maxit, s));
         return SEM_OK;
     }
     const int64_t n = L.nL;
@@ -685,7 +746,8 @@ static int vcycle(sem_handle h, int l, const SolveCfg &cfg, hipStream_t s)
     SEM_TRY(chebyshev(L, l, h, r, x, true, lmin_f * lmax, lmax_f * lmax, cfg.deg, cfg.h1, cfg.h2, s));
     // restricted residual s = W (r - A x)
     SEM_TRY(apply_f32(L, x, t, cfg.h1, cfg.h2, s));
-    LAUNCH_V(wresid_kernel, n, s, n, L.W32, r, t, sres);
+    LAUNCH_V(wresid_fused_kernel, n, s, n, L.W32, (const float *)r, (const float *)t,
+             (const int32_t *)nullptr, L.perm, L.offs, sres);
     const Level &C = h->lv[l + 1];
     const int64_t nc = C.nL;
     if (l + 1 == lc) {
@@ -817,9 +879,11 @@ int pcg_solve(sem_handle h, const double *b, double *x, const sem_solve_opts *o,
         SEM_TRY(pcg_start(F, o->k, o->h1, o->h2, b, x, o->zero_guess != 0, w.r, w.p, w.w, w.partial,
                           w.sc, o->tol, o->maxit, s));
         SEM_TRY(read_scalars(h, w.sc, &hs, s));
+        int it = 0;
         while (!hs.done) {
-            SEM_TRY(pcg_iterations(F, o->k, o->h1, o->h2, x, w.r, w.p, w.w, w.partial, w.sc,
-                                   cfg.check_every, s));
+            SEM_TRY(pcg_iterations(F, o->k, o->h1, o->h2, x, w.r, w.p, w.w, w.partial_ax, w.partial,
+                                   w.sc, it + 1, cfg.check_every, s));
+            it += cfg.check_every;
             SEM_TRY(read_scalars(h, w.sc, &hs, s));
         }
     } else {
@@ -839,24 +903,28 @@ int pcg_solve(sem_handle h, const double *b, double *x, const sem_solve_opts *o,
         const int nbv = red_grid(n);
         if (!hs.done) {
             SEM_TRY(precondition_pmg(h, w.r, w.z, cfg, s));
-            LAUNCH_V(dot2_kernel, n, s, n, w.sc, F.W, w.z, w.r, w.r, w.partial);
-            LAUNCH_1(fin_rz_kernel, s, w.partial, (int64_t)nbv, w.sc);
-            LAUNCH_V(fcg_p_kernel, n, s, n, w.sc, w.z, w.p, 1);
+            LAUNCH_V(dot_zw_kernel, n, s, n, (const KrylovScalars *)w.sc, F.W, (const double *)w.z,
+                     (const double *)w.r, (const double *)w.r, w.partial);
+            LAUNCH_V(fcg_p_fused_kernel, n, s, n, w.sc, 1, (const double *)w.partial, (int64_t)nbv,
+                     (const double *)w.z, w.p, 1);
         }
-        while (!hs.done) {
+        for (int it = 0; !hs.done; ++it) {
+            const int parity = it & 1;
             int64_t nbax = 0;
-            SEM_TRY(launch_ax<double>(F, F.G, F.B, F.D, w.p, w.w, o->h1, o->h2, nullptr, w.partial,
+            SEM_TRY(launch_ax<double>(F, F.G, F.B, F.D, w.p, w.w, o->h1, o->h2, nullptr, w.partial_ax,
                                       &nbax, s, &w.sc->done));
             SEM_TRY(launch_gs<double>(F, w.w, s, &w.sc->done));
-            LAUNCH_1(fin_alpha_kernel, s, w.partial, nbax, w.sc);
-            LAUNCH_V(fcg_update_kernel, n, s, n, w.sc, w.p, w.w, F.W, x, w.r, w.partial);
+            LAUNCH_V(fcg_update_fused_kernel, n, s, n, w.sc, parity, (const double *)w.partial_ax,
+                     nbax, (const double *)w.p, (const double *)w.w, (const int32_t *)nullptr, F.perm,
+                     F.offs, F.W, x, w.r, w.partial);
             LAUNCH_1(fin_conv_kernel, s, w.partial, (int64_t)nbv, w.sc);
             SEM_TRY(read_scalars(h, w.sc, &hs, s));
             if (hs.done) break;
             SEM_TRY(precondition_pmg(h, w.r, w.z, cfg, s));
-            LAUNCH_V(dot2_kernel, n, s, n, w.sc, F.W, w.z, w.w, w.r, w.partial);
-            LAUNCH_1(fin_beta_fcg_kernel, s, w.partial, (int64_t)nbv, w.sc);
-            LAUNCH_V(fcg_p_kernel, n, s, n, w.sc, w.z, w.p, 0);
+            LAUNCH_V(dot_zw_kernel, n, s, n, (const KrylovScalars *)w.sc, F.W, (const double *)w.z,
+                     (const double *)w.w, (const double *)w.r, w.partial);
+            LAUNCH_V(fcg_p_fused_kernel, n, s, n, w.sc, parity, (const double *)w.partial,
+                     (int64_t)nbv, (const double *)w.z, w.p, 0);
             KrylovScalars csc{};
             SEM_HIP(hipMemcpyAsync(&w.host_sc[1], w.sc_c, sizeof(KrylovScalars), hipMemcpyDeviceToHost, s));
             SEM_TRY(read_scalars(h, w.sc, &hs, s));
@@ -888,11 +956,64 @@ int pcg_solve(sem_handle h, const double *b, double *x, const sem_solve_opts *o,
     return SEM_OK;
 }
 
+// b = R QQ^T (B o f)
+int assemble_load(sem_handle h, const double *f, double *b, hipStream_t s)
+{
+    const Level &F = h->lv[0];
+    const int64_t n = F.nL;
+    LAUNCH_V(mass_kernel, n, s, n, F.B, f, b);
+    SEM_TRY(launch_gs<double>(F, b, s));
+    LAUNCH_V((mask_kernel<double, double>), n, s, n, F.W, b);
+    return SEM_OK;
+}
+
+int adjoint(sem_handle h, const double *u, const double *g, const sem_solve_opts *o, double *lam,
+            double *grad_f, double *grad_k, sem_solve_stats *st, hipStream_t s)
+{
+    const Level &F = h->lv[0];
+    const int64_t n = F.nL;
+    SEM_TRY(ensure_workspace(h, false));
+    if (!h->ws.aux) SEM_HIP(hipMalloc(&h->ws.aux, sizeof(double) * n));
+    // right-hand side R QQ^T g in a workspace vector the solver does not touch
+    double *rhs = h->ws.aux;
+    SEM_HIP(hipMemcpyAsync(rhs, g, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    SEM_TRY(launch_gs<double>(F, rhs, s));
+    LAUNCH_V((mask_kernel<double, double>), n, s, n, F.W, rhs);
+    sem_solve_opts oo = *o;
+    oo.zero_guess = 1;
+    if (oo.k != nullptr || h->n_levels < 2) oo.precond = SEM_PRECOND_JACOBI;
+    const int rc = pcg_solve(h, rhs, lam, &oo, st, s);
+    if (rc != SEM_OK && rc != SEM_ENOCONV) return rc;
+    if (grad_f) LAUNCH_V(mass_kernel, n, s, n, F.B, lam, grad_f);
+    if (grad_k) SEM_TRY(launch_grad_k(F, u, lam, o->h1, grad_k, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    return rc;
+}
+
 }  // namespace semx
 
 using namespace semx;
 
 extern "C" {
+
+int sem_rhs(sem_handle h, const double *f, double *b, void *stream)
+{
+    if (!h || !f || !b) {
+        set_error("sem_rhs: null argument");
+        return SEM_EINVAL;
+    }
+    return assemble_load(h, f, b, (hipStream_t)stream);
+}
+
+int sem_adjoint(sem_handle h, const double *u, const double *g, const sem_solve_opts *o,
+                double *lam, double *grad_f, double *grad_k, sem_solve_stats *st, void *stream)
+{
+    if (!h || !u || !g || !o || !lam) {
+        set_error("sem_adjoint: null argument");
+        return SEM_EINVAL;
+    }
+    return adjoint(h, u, g, o, lam, grad_f, grad_k, st, (hipStream_t)stream);
+}
 
 void sem_solve_opts_default(sem_solve_opts *o)
 {

@@ -83,6 +83,9 @@ _SIGS = {
     "sem_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(SemSolveOpts),
                                      ctypes.POINTER(SemSolveStats), _VP]),
     "sem_grad_k": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
+    "sem_rhs": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "sem_adjoint": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(SemSolveOpts), _VP, _VP, _VP,
+                                   ctypes.POINTER(SemSolveStats), _VP]),
     "sem_info": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(SemInfo)]),
     "sem_get_maps": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
     "sem_get_geometry": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
@@ -168,6 +171,7 @@ class Sem:
     def __init__(self, mesh, levels=None):
         torch = _torch()
         L = lib()
+        self._h = None
         self.N = int(mesh.N)
         nq = self.N + 1
         self._x = np.ascontiguousarray(mesh.x, dtype=np.float64).reshape(-1)
@@ -187,7 +191,12 @@ class Sem:
         self.levels = tuple(levels) if levels is not None else (self.N,)
         h = ctypes.c_void_p()
         self.device = torch.cuda.current_device()
-        _check(L.sem_setup(ctypes.byref(m), ctypes.byref(opts), _stream(), ctypes.byref(h)), "sem_setup")
+        try:
+            _check(L.sem_setup(ctypes.byref(m), ctypes.byref(opts), _stream(), ctypes.byref(h)),
+                   "sem_setup")
+        finally:
+            # the library copied the mesh; drop the host copies
+            del self._x, self._y, self._z, self._g, self._d
         self._h = h
         self.info0 = self.info(0)
 
@@ -262,12 +271,10 @@ class Sem:
         lib().sem_solve_opts_default(ctypes.byref(o))
         return o
 
-    def solve(self, b, x=None, raise_on_error=True, **kw):
-        """Solve R(h1 A(k) + h2 B)R^T x = R b; returns (x, stats dict, status).
-        Keyword options are the fields of sem_solve_opts (k as a tensor,
-        precond as "jacobi"/"pmg")."""
+    def _opts(self, kw):
         torch = _torch()
         o = self.default_opts()
+        kw = dict(kw)
         kk = kw.pop("k", None)
         pre = kw.pop("precond", None)
         if pre is not None:
@@ -278,6 +285,42 @@ class Sem:
             setattr(o, name, val)
         if kk is not None:
             o.k = _dev_ptr(kk, torch.float64, self.n_local, "k").value
+        return o
+
+    def rhs(self, f, out=None):
+        """b = R QQ^T (B f): the assembled load of the weak form."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(f)
+        _check(lib().sem_rhs(self._handle(), _dev_ptr(f, torch.float64, self.n_local, "f"),
+                             _dev_ptr(out, torch.float64, self.n_local, "b"), _stream()), "sem_rhs")
+        return out
+
+    def adjoint(self, u, g, need_grad_k=True, raise_on_error=True, **kw):
+        """lam = A^{-1} R QQ^T g, grad_f = B lam, grad_k = -(D lam)^T G (D u).
+        Returns (lam, grad_f, grad_k or None, stats, status)."""
+        torch = _torch()
+        o = self._opts(kw)
+        lam = torch.empty_like(u)
+        gf = torch.empty_like(u)
+        gk = torch.empty_like(u) if need_grad_k else None
+        st = SemSolveStats()
+        rc = lib().sem_adjoint(self._handle(), _dev_ptr(u, torch.float64, self.n_local, "u"),
+                               _dev_ptr(g, torch.float64, self.n_local, "g"), ctypes.byref(o),
+                               _dev_ptr(lam, torch.float64, self.n_local, "lam"),
+                               _dev_ptr(gf, torch.float64, self.n_local, "grad_f"),
+                               None if gk is None else _dev_ptr(gk, torch.float64, self.n_local, "grad_k"),
+                               ctypes.byref(st), _stream())
+        if raise_on_error and rc not in (SEM_OK, SEM_ENOCONV):
+            _check(rc, "sem_adjoint")
+        return lam, gf, gk, st.as_dict(), rc
+
+    def solve(self, b, x=None, raise_on_error=True, **kw):
+        """Solve R(h1 A(k) + h2 B)R^T x = R b; returns (x, stats dict, status).
+        Keyword options are the fields of sem_solve_opts (k as a tensor,
+        precond as "jacobi"/"pmg")."""
+        torch = _torch()
+        o = self._opts(kw)
         if x is None:
             x = torch.zeros_like(b)
             o.zero_guess = 1

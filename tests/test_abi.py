@@ -23,7 +23,7 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for required in ("sem_setup", "sem_ax", "sem_gs", "sem_pcg_solve", "sem_grad_k", "sem_free",
-                     "sem_strerror", "sem_last_error"):
+                     "sem_rhs", "sem_adjoint", "sem_strerror", "sem_last_error"):
         assert required in names
     assert len(names) >= 16
 
@@ -100,6 +100,13 @@ def test_host_error_paths():
     o = S.Sem.default_opts()
     assert L.sem_pcg_solve(None, None, None, ctypes.byref(o), None, None) == S.SEM_EINVAL
     assert L.sem_free(None) == 0
+    assert L.sem_rhs(None, None, None, None) == S.SEM_EINVAL
+    assert L.sem_adjoint(None, None, None, ctypes.byref(o), None, None, None, None, None) == S.SEM_EINVAL
+    assert L.sem_grad_k(None, None, None, 1.0, None, None) == S.SEM_EINVAL
+    assert L.sem_ax_level(None, 0, 0, None, None, 1.0, 0.0, None) == S.SEM_EINVAL
+    assert L.sem_gs_level(None, 0, 0, None, None) == S.SEM_EINVAL
+    info = S.SemInfo()
+    assert L.sem_info(None, 0, ctypes.byref(info)) == S.SEM_EINVAL
 
 
 def test_default_solver_options():

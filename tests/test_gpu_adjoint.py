@@ -1,0 +1,131 @@
+"""GPU tests of the hand-written adjoint (sem_adjoint + SemSolve autograd):
+against the CPU oracle's adjoint gradient, and against central finite
+differences of the loss 1/2 ||u - u_t||_B^2 (step 1e-6) for
+-div(k grad u) = f on deformed boxes with k = exp(0.5 g)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import solvers
+from paper_2104_05829_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2104_05829_amd import Sem, SemSolve  # noqa: E402
+
+
+def _case(shape, N, gll_nodes):
+    m = inputs.box_mesh(*shape, gll_nodes, deform="cyclic")
+    g = inputs.fourier_field(m.x, m.y, m.z, 4, 40).reshape(-1)
+    k = np.exp(0.5 * g)
+    f = 1.0 + inputs.fourier_field(m.x, m.y, m.z, 4, 41).reshape(-1)
+    ut = inputs.sin3(m.x, m.y, m.z).reshape(-1)
+    return m, k, f, ut
+
+
+def _loss_fn(sem):
+    W, _ = sem.weights()
+    _, B = sem.geometry()
+    Bbar = sem.gs(B.clone())
+
+    def loss(u, ut):
+        d = u - ut
+        return 0.5 * torch.sum(W * Bbar * d * d)
+    return loss
+
+
+OPTS = dict(tol=1e-13, maxit=20000, h1=1.0, h2=0.0)
+
+
+@pytest.mark.parametrize("recompute", [False, True])
+def test_adjoint_matches_oracle(recompute):
+    print(f"[gpu] adjoint vs oracle recompute={recompute}", flush=True)
+    N = 5
+    xi, _ = oracle.gll(N)
+    m, k, f, ut = _case((3, 2, 2), N, xi)
+    L, u_o, lam_o, gf_o, gk_o, _, _ = solvers.adjoint_loss_grad(m, N, f, k, ut, tol=1e-14)
+    s = Sem(m)
+    fd = torch.tensor(f, device="cuda", requires_grad=True)
+    kd = torch.tensor(k, device="cuda", requires_grad=True)
+    u = SemSolve.apply(fd, kd, s, OPTS, recompute)
+    loss = _loss_fn(s)(u, torch.tensor(ut, device="cuda"))
+    loss.backward()
+    assert abs(loss.item() - L) <= 1e-10 * abs(L)
+    np.testing.assert_allclose(u.detach().cpu().numpy(), u_o, atol=1e-11 * np.abs(u_o).max())
+    gf = fd.grad.cpu().numpy()
+    gk = kd.grad.cpu().numpy()
+    assert np.max(np.abs(gf - gf_o)) <= 1e-9 * np.max(np.abs(gf_o))
+    assert np.max(np.abs(gk - gk_o)) <= 1e-9 * np.max(np.abs(gk_o))
+    s.free()
+
+
+def test_adjoint_central_differences_c4():
+    """8x8x8 deformed box, N=7: dL/df and dL/dk against central differences
+    with h = 1e-6.  Directions: seeded N(0,1) entries (rng(42)), and the unit
+    direction along the gradient.  The FD quotient carries an absolute error
+    of about eps_L / h, eps_L being the loss error left by the solves (about
+    1e-18 here, so ~1e-12 after dividing by h); these directions have
+    directional derivatives of order 1e-5, so agreement to 1e-6 relative is
+    meaningful.  Sampled single entries (the largest |dL/dk|, about 8e-7 each)
+    sit within a factor of 1e6 of that noise floor, so they are judged at
+    1e-5 of max |dL/dk|."""
+    print("[gpu] adjoint FD 8^3 N=7", flush=True)
+    N = 7
+    xi, _ = oracle.gll(N)
+    m, k, f, ut = _case((8, 8, 8), N, xi)
+    s = Sem(m)
+    loss_fn = _loss_fn(s)
+    utd = torch.tensor(ut, device="cuda")
+    fd = torch.tensor(f, device="cuda", requires_grad=True)
+    kd = torch.tensor(k, device="cuda", requires_grad=True)
+    u = SemSolve.apply(fd, kd, s, OPTS, True)
+    loss = loss_fn(u, utd)
+    loss.backward()
+    gf, gk = fd.grad.detach(), kd.grad.detach()
+
+    def L(fv, kv):
+        with torch.no_grad():
+            uu = SemSolve.apply(fv, kv, s, OPTS, False)
+            return loss_fn(uu, utd).item()
+
+    h = 1e-6
+    rng = np.random.default_rng(42)
+    f0 = fd.detach()
+    k0 = kd.detach()
+    worst = 0.0
+    dirs = [torch.tensor(rng.standard_normal(f.size), device="cuda") for _ in range(3)]
+    for which, grad in (("f", gf), ("k", gk)):
+        for d in dirs + [grad / torch.linalg.norm(grad)]:
+            if which == "f":
+                num = (L(f0 + h * d, k0) - L(f0 - h * d, k0)) / (2 * h)
+            else:
+                num = (L(f0, k0 + h * d) - L(f0, k0 - h * d)) / (2 * h)
+            an = float(torch.dot(grad, d))
+            rel = abs(num - an) / abs(an)
+            worst = max(worst, rel)
+            assert rel <= 1e-6, (which, num, an, rel)
+    gmax = float(gk.abs().max())
+    for q in torch.topk(gk.abs(), 4).indices.tolist():
+        e = torch.zeros_like(k0)
+        e[q] = 1.0
+        num = (L(f0, k0 + h * e) - L(f0, k0 - h * e)) / (2 * h)
+        assert abs(num - float(gk[q])) <= 1e-5 * gmax, ("k entry", q, num, float(gk[q]))
+    print(f"[gpu] worst relative FD discrepancy {worst:.2e}", flush=True)
+    s.free()
+
+
+def test_rhs_matches_oracle():
+    N = 7
+    xi, _ = oracle.gll(N)
+    m, k, f, ut = _case((3, 3, 3), N, xi)
+    s = Sem(m)
+    b = s.rhs(torch.tensor(f, device="cuda")).cpu().numpy()
+    lv = solvers.Level(N, m.x, m.y, m.z, m.gid, m.dirichlet)
+    ref = lv.rhs(f)
+    assert np.max(np.abs(b - ref)) <= 1e-14 * np.max(np.abs(ref))
+    assert np.all(b[m.dirichlet.reshape(-1) == 1] == 0.0)
+    s.free()
