@@ -216,6 +216,97 @@ def bench_large(args, torch, sem_mod, inputs):
     return out
 
 
+def bench_c1(args, torch, sem_mod, inputs, with_cpu):
+    """4x4x4 undeformed unit cube, N=7, Poisson, homogeneous Dirichlet,
+    f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z); Jacobi-PCG to 1e-10.  A latency
+    configuration (2 MB per operator apply)."""
+    import math
+    mesh = sem_mod.box_mesh(4, 4, 4, 7)
+    s = sem_mod.Sem(mesh)
+    ue = inputs.sin3(mesh.x, mesh.y, mesh.z).reshape(-1)
+    f = torch.tensor(3 * math.pi ** 2 * ue, device="cuda")
+    b = s.rhs(f)
+    s.solve(b, tol=1e-10)  # warm-up, builds the Jacobi diagonal
+    reps = 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        x, st, rc = s.solve(b, tol=1e-10)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    err = float(torch.max(torch.abs(x - torch.tensor(ue, device="cuda"))))
+    out = {"workload": "4x4x4 undeformed unit cube, N=7, Poisson, Jacobi-PCG to 1e-10",
+           "ms": round(ms, 3), "iters": st["iters"], "true_rel_res": float(f"{st['true_rel_res']:.3e}"),
+           "max_err_vs_exact": float(f"{err:.3e}"), "status": rc}
+    if with_cpu:
+        import oracle
+        from oracle import solvers
+        xi, _ = oracle.gll(7)
+        m = inputs.box_mesh(4, 4, 4, xi)
+        lv = solvers.Level(7, m.x, m.y, m.z, m.gid, m.dirichlet)
+        bo = lv.rhs(3 * math.pi ** 2 * ue)
+        t0 = time.perf_counter()
+        _, ito, _ = solvers.pcg_jacobi(lv, bo, tol=1e-10)
+        out["cpu_oracle"] = {"ms": round((time.perf_counter() - t0) * 1e3, 1), "iters": ito,
+                             "cores": 1, "kind": "oracle"}
+    s.free()
+    return out
+
+
+def bench_adjoint(args, torch, sem_mod, inputs):
+    """8x8x8 deformed box, N=7: -div(k grad u) = f with k = exp(0.5 g), loss
+    1/2 ||u - u_t||_B^2; forward + backward (hand-written adjoint) time, and
+    central differences (h = 1e-6) along one seeded N(0,1) direction for f and
+    one for k."""
+    from paper_2104_05829_amd import SemSolve
+    mesh = sem_mod.box_mesh(8, 8, 8, 7, deform="cyclic", amp=0.05)
+    s = sem_mod.Sem(mesh)
+    g = inputs.fourier_field(mesh.x, mesh.y, mesh.z, 4, 40).reshape(-1)
+    kk = torch.tensor(np.exp(0.5 * g), device="cuda")
+    ff = torch.tensor(1.0 + inputs.fourier_field(mesh.x, mesh.y, mesh.z, 4, 41).reshape(-1),
+                      device="cuda")
+    ut = torch.tensor(inputs.sin3(mesh.x, mesh.y, mesh.z).reshape(-1), device="cuda")
+    W, _ = s.weights()
+    _, B = s.geometry()
+    Bbar = s.gs(B.clone())
+    opts = dict(tol=1e-13, maxit=20000)
+
+    def loss_of(u):
+        d = u - ut
+        return 0.5 * torch.sum(W * Bbar * d * d)
+
+    def fwd_bwd():
+        f = ff.clone().requires_grad_(True)
+        k = kk.clone().requires_grad_(True)
+        L = loss_of(SemSolve.apply(f, k, s, opts, False))
+        L.backward()
+        return L.item(), f.grad, k.grad
+
+    fwd_bwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L, gf, gk = fwd_bwd()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+
+    def Lval(f, k):
+        with torch.no_grad():
+            return loss_of(SemSolve.apply(f, k, s, opts, False)).item()
+
+    rng = np.random.default_rng(42)
+    h = 1e-6
+    d = torch.tensor(rng.standard_normal(ff.numel()), device="cuda")
+    dk = torch.tensor(rng.standard_normal(kk.numel()), device="cuda")
+    fd_f = (Lval(ff + h * d, kk) - Lval(ff - h * d, kk)) / (2 * h)
+    fd_k = (Lval(ff, kk + h * dk) - Lval(ff, kk - h * dk)) / (2 * h)
+    an_f, an_k = float(torch.dot(gf, d)), float(torch.dot(gk, dk))
+    s.free()
+    return {"workload": "8x8x8 deformed box, N=7, variable-coefficient Poisson, loss 1/2||u-u_t||_B^2",
+            "ms_forward_backward": round(ms, 2), "loss": L,
+            "fd_rel_discrepancy_f": float(f"{abs(fd_f - an_f) / abs(an_f):.3e}"),
+            "fd_rel_discrepancy_k": float(f"{abs(fd_k - an_k) / abs(an_k):.3e}")}
+
+
 def cpu_baseline(mesh, seconds):
     """The oracle's Ax + QQ^T on the full 16^3 N=7 mesh, repeated until
     about `seconds` of CPU time; single-threaded C (no OpenMP)."""
@@ -245,6 +336,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the 4^3 and adjoint records")
     ap.add_argument("--pcg-elems", type=int, default=32)
     ap.add_argument("--pcg-rhs", type=int, default=3)
     ap.add_argument("--coarse-tol", type=float, default=1e-2)
@@ -329,6 +421,10 @@ def main():
     if not args.no_pcg:
         log("[bench] pcg: 32^3 Helmholtz, FCG+FP32 p-MG vs FP64 Jacobi-PCG to 1e-8")
         line["pcg"] = bench_pcg(args, torch, sem_mod, inputs)
+    if not args.no_small:
+        log("[bench] 4^3 Poisson Jacobi-PCG and 8^3 adjoint")
+        line["c1"] = bench_c1(args, torch, sem_mod, inputs, not args.no_cpu)
+        line["adjoint"] = bench_adjoint(args, torch, sem_mod, inputs)
     if args.large:
         log("[bench] large: 64x64x32 Poisson, FCG+FP32 p-MG vs FP64 Jacobi-PCG to 1e-8")
         line["pcg_large"] = bench_large(args, torch, sem_mod, inputs)

@@ -10,6 +10,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <vector>
 
 #include "sem_internal.h"
 
@@ -206,6 +207,66 @@ int build_maps(Level &L, const int64_t *gid, const uint8_t *dir, const double *x
                        L.W, L.W32);
     SEM_HIP(hipGetLastError());
     SEM_HIP(hipStreamSynchronize(s));
+    return build_gs_chunks(L, s);
+}
+
+// Pack whole segments, in canonical order, into chunks of at most 64 copies
+// (one wavefront each): chunk c covers perm[cstart[c] .. cstart[c+1]) and
+// bit l of cmask[c] marks lane l as the first copy of a segment.  Segments
+// with more than 64 copies go to an overflow list handled one thread per
+// segment.  Greedy on the host: O(segments), setup only.
+int build_gs_chunks(Level &L, hipStream_t s)
+{
+    std::vector<int32_t> offs(L.nseg + 1);
+    if (L.nseg > 0)
+        SEM_HIP(hipMemcpy(offs.data(), L.offs, sizeof(int32_t) * (L.nseg + 1), hipMemcpyDeviceToHost));
+    else
+        offs[0] = 0;
+    std::vector<int32_t> cb, ce;
+    std::vector<uint64_t> cmask;
+    std::vector<int32_t> over;
+    int32_t cur = -1, used = 0;
+    uint64_t mask = 0;
+    for (int64_t q = 0; q < L.nseg; ++q) {
+        const int32_t a = offs[q], len = offs[q + 1] - offs[q];
+        if (len > 64) {
+            over.push_back((int32_t)q);
+            continue;
+        }
+        if (cur < 0 || used + len > 64 || a != cur + used) {
+            if (cur >= 0) {
+                cb.push_back(cur);
+                ce.push_back(cur + used);
+                cmask.push_back(mask);
+            }
+            cur = a;
+            used = 0;
+            mask = 0;
+        }
+        mask |= 1ULL << used;
+        used += len;
+    }
+    if (cur >= 0) {
+        cb.push_back(cur);
+        ce.push_back(cur + used);
+        cmask.push_back(mask);
+    }
+    const int64_t nch = (int64_t)cmask.size();
+    L.nchunks = nch;
+    L.nover = (int64_t)over.size();
+    if (nch > 0) {
+        SEM_HIP(hipMalloc(&L.chunk_b, sizeof(int32_t) * nch));
+        SEM_HIP(hipMalloc(&L.chunk_e, sizeof(int32_t) * nch));
+        SEM_HIP(hipMalloc(&L.chunk_mask, sizeof(uint64_t) * nch));
+        SEM_HIP(hipMemcpy(L.chunk_b, cb.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice));
+        SEM_HIP(hipMemcpy(L.chunk_e, ce.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice));
+        SEM_HIP(hipMemcpy(L.chunk_mask, cmask.data(), sizeof(uint64_t) * nch, hipMemcpyHostToDevice));
+    }
+    if (L.nover > 0) {
+        SEM_HIP(hipMalloc(&L.over, sizeof(int32_t) * L.nover));
+        SEM_HIP(hipMemcpy(L.over, over.data(), sizeof(int32_t) * L.nover, hipMemcpyHostToDevice));
+    }
+    (void)s;
     return SEM_OK;
 }
 

@@ -4,13 +4,20 @@
 namespace semx {
 
 // ---------------------------------------------------------------------------
-// QQ^T (Sec. 2.3 eq. (dssum); gs_op(+) of Sec. 3.2) over the sorted maps: one
-// thread per shared global node (segment).  The copies of a segment are listed
-// in ascending local index, the sum starts from 0 and adds them in that order,
-// then every copy receives it.  Unshared copies are never touched.
+// QQ^T (Sec. 2.3 eq. (dssum); gs_op(+) of Sec. 3.2) as a segmented reduction
+// over the sorted maps.  The shared copies (perm, canonical order) are packed
+// into chunks of whole segments of at most 64 copies; one 64-lane wavefront
+// takes one chunk: lane l loads copy l (coalesced perm load, one gathered
+// value), then sums the lanes of its segment in ascending order by cross-lane
+// reads and writes the total back.  Each sum starts from 0 and adds the
+// copies in ascending local index order, so the result is bit-identical to a
+// sequential pass.  Unshared copies are never touched.  Segments with more
+// than 64 copies (not in conforming hex meshes of moderate valence) go to a
+// one-thread-per-segment pass.
 // ---------------------------------------------------------------------------
+
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2;
-// give XCD x the x-th contiguous chunk of segments so that neighbouring
+// give XCD x the x-th contiguous range of workgroups so that neighbouring
 // segments (which share cache lines of the L-vector) meet in one L2.
 __device__ inline int64_t xcd_chunk_block(int64_t b, int64_t nb)
 {
@@ -19,14 +26,51 @@ __device__ inline int64_t xcd_chunk_block(int64_t b, int64_t nb)
     return x * per + (x < rem ? x : rem) + q;
 }
 
+constexpr int kGsWavesPerBlock = 4;
+
 template <typename T>
-__global__ void gs_kernel(int64_t nseg, const int32_t *__restrict__ perm,
-                          const int32_t *__restrict__ offs, T *__restrict__ v,
-                          const int *__restrict__ skip)
+__global__ void __launch_bounds__(64 * kGsWavesPerBlock)
+gs_chunk_kernel(int64_t nchunks, const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
+                const uint64_t *__restrict__ cmask, const int32_t *__restrict__ perm,
+                T *__restrict__ v, const int *__restrict__ skip)
 {
     if (skip != nullptr && *skip != 0) return;
-    const int64_t sidx = xcd_chunk_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (sidx >= nseg) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t c = xcd_chunk_block(blockIdx.x, gridDim.x) * kGsWavesPerBlock + (threadIdx.x >> 6);
+    if (c >= nchunks) return;  // uniform per wavefront
+    const int b = cb[c];
+    const int cnt = ce[c] - b;
+    const bool act = lane < cnt;
+    const int idx = act ? perm[b + lane] : 0;
+    const T val = act ? v[idx] : T(0);
+    const uint64_t m = cmask[c];  // bit l: lane l starts a segment (bit 0 always set)
+    const uint64_t upto = (lane == 63) ? ~0ULL : ((2ULL << lane) - 1ULL);
+    const int s0 = 63 - __clzll((long long)(m & upto));      // first lane of my segment
+    const uint64_t above = m & ~upto;
+    const int e0 = above ? (__ffsll((long long)above) - 1) : cnt;  // one past its last lane
+    const int len = act ? e0 - s0 : 0;
+    int maxlen = len;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o));
+    T acc = T(0);
+    for (int j = 0; j < maxlen; ++j) {  // wave-uniform trip count
+        const T other = __shfl(val, min(s0 + j, 63));
+        if (j < len) acc += other;
+    }
+    if (act) v[idx] = acc;
+}
+
+// segments listed in `segs`, one thread each (copies in canonical order)
+template <typename T>
+__global__ void gs_segment_kernel(int64_t nseg, const int32_t *__restrict__ segs,
+                                  const int32_t *__restrict__ perm,
+                                  const int32_t *__restrict__ offs, T *__restrict__ v,
+                                  const int *__restrict__ skip)
+{
+    if (skip != nullptr && *skip != 0) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nseg) return;
+    const int sidx = segs[t];
     const int a = offs[sidx], b = offs[sidx + 1];
     T acc = T(0);
     for (int o = a; o < b; ++o) acc += v[perm[o]];
@@ -36,11 +80,19 @@ __global__ void gs_kernel(int64_t nseg, const int32_t *__restrict__ perm,
 template <typename T>
 int launch_gs(const Level &L, T *v, hipStream_t s, const int *skip)
 {
-    if (L.nseg == 0) return SEM_OK;
-    const int bs = 256;
-    const int64_t nb = (L.nseg + bs - 1) / bs;
-    hipLaunchKernelGGL(gs_kernel<T>, dim3((unsigned)nb), dim3(bs), 0, s, L.nseg, L.perm, L.offs, v, skip);
-    SEM_HIP(hipGetLastError());
+    if (L.nchunks > 0) {
+        const int64_t nb = (L.nchunks + kGsWavesPerBlock - 1) / kGsWavesPerBlock;
+        hipLaunchKernelGGL(gs_chunk_kernel<T>, dim3((unsigned)nb), dim3(64 * kGsWavesPerBlock), 0, s,
+                           L.nchunks, L.chunk_b, L.chunk_e, L.chunk_mask, L.perm, v, skip);
+        SEM_HIP(hipGetLastError());
+    }
+    if (L.nover > 0) {
+        const int bs = 256;
+        const int64_t nb = (L.nover + bs - 1) / bs;
+        hipLaunchKernelGGL(gs_segment_kernel<T>, dim3((unsigned)nb), dim3(bs), 0, s, L.nover, L.over,
+                           L.perm, L.offs, v, skip);
+        SEM_HIP(hipGetLastError());
+    }
     return SEM_OK;
 }
 template int launch_gs<double>(const Level &, double *, hipStream_t, const int *);

@@ -69,6 +69,11 @@ struct Level {
     uint8_t *dir = nullptr;
     int32_t *perm = nullptr, *offs = nullptr;
     int32_t *segid = nullptr;  // per copy: segment of its node in perm, -1 if unshared
+    // wavefront chunks of whole segments for the gather-scatter kernel
+    int64_t nchunks = 0, nover = 0;
+    int32_t *chunk_b = nullptr, *chunk_e = nullptr;  // perm range of each chunk
+    uint64_t *chunk_mask = nullptr;                   // segment-start lanes
+    int32_t *over = nullptr;                          // segments longer than 64 copies
     double *D = nullptr;   // Dh [nq][nq] (row = point)
     float *D32 = nullptr;
     // interpolation from the next coarser level's nodes to this level's
@@ -152,6 +157,7 @@ int launch_interp(int64_t E, int ns, int nt, const T *J, const T *in, T *out, bo
 // setup helpers
 int build_maps(Level &L, const int64_t *gid_dev, const uint8_t *dir_dev, const double *x,
                const double *y, const double *z, int *bad_dev, hipStream_t s);
+int build_gs_chunks(Level &L, hipStream_t s);
 
 int host_gll(int N, double *xi, double *rho, double *D);
 void host_interp(int ns, const double *xs, int nt, const double *xt, double *J);

@@ -284,3 +284,30 @@ def test_grad_k_parity():
     r2, rmax = _rel(gk, ref)
     assert r2 <= 1e-12 and rmax <= 1e-12
     s.free()
+
+
+def test_gs_nodes_with_more_than_64_copies():
+    """80 coincident elements whose nodes share global pointers (80 copies per
+    node, beyond one wavefront chunk) plus a second block of ordinary shared
+    nodes: QQ^T stays bit-exact."""
+    print("[gpu] gs overflow segments", flush=True)
+    N = 2
+    xi, _ = oracle.gll(N)
+    one = inputs.box_mesh(1, 1, 1, xi)
+    two = inputs.box_mesh(2, 1, 1, xi)
+    reps = 80
+    x = np.concatenate([np.repeat(one.x, reps, axis=0), two.x])
+    y = np.concatenate([np.repeat(one.y, reps, axis=0), two.y])
+    z = np.concatenate([np.repeat(one.z, reps, axis=0), two.z + 5.0])
+    gid = np.concatenate([np.repeat(one.gid, reps, axis=0), two.gid + 1000])
+    m = inputs.BoxMesh(N=N, shape=(reps + 2, 1, 1), x=x, y=y, z=z, gid=gid,
+                       dirichlet=np.zeros(gid.shape, dtype=np.uint8))
+    s = Sem(m)
+    v = inputs.uniform_lvector(gid.size, 8)
+    out = _host(s.gs(_dev(v)))
+    np.testing.assert_array_equal(out, oracle.qqt(gid, v))
+    perm, offs = s.maps()
+    po, oo = oracle.gs_maps(gid)
+    np.testing.assert_array_equal(_host(perm), po)
+    np.testing.assert_array_equal(_host(offs), oo)
+    s.free()
