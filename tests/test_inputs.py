@@ -1,0 +1,66 @@
+"""The seeded input generators: box meshes (copies of a node coincide bit
+for bit, structured pointers, topological Dirichlet flags), the library's
+mesh against the oracle's, and the random fields.  CPU only."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_05829_amd import inputs
+from paper_2104_05829_amd import sem as S
+
+
+@pytest.mark.parametrize("deform", [None, "cyclic"])
+def test_box_mesh_copies_coincide(deform):
+    xi, _ = oracle.gll(5)
+    m = inputs.box_mesh(3, 2, 4, xi, L=(1.0, 0.7, 1.3), origin=(0.1, 0.2, -0.3), deform=deform)
+    g = m.gid.reshape(-1)
+    for arr in (m.x, m.y, m.z, m.dirichlet):
+        a = arr.reshape(-1)
+        order = np.argsort(g, kind="stable")
+        gs, as_ = g[order], a[order]
+        first = np.r_[True, gs[1:] != gs[:-1]]
+        rep = np.maximum.accumulate(np.where(first, np.arange(g.size), 0))
+        np.testing.assert_array_equal(as_, as_[rep])
+    assert g.min() == 1 and len(np.unique(g)) == m.n_unique
+    # Dirichlet copies are exactly the structured boundary
+    xs = m.x.reshape(-1)
+    if deform is None:
+        on = (np.isclose(m.x, 0.1) | np.isclose(m.x, 1.1) | np.isclose(m.y, 0.2) | np.isclose(m.y, 0.9)
+              | np.isclose(m.z, -0.3) | np.isclose(m.z, 1.0))
+        np.testing.assert_array_equal(on.reshape(-1), m.dirichlet.reshape(-1).astype(bool))
+    assert xs.size == m.E * 216
+
+
+def test_library_mesh_matches_oracle_mesh():
+    lib_mesh = S.box_mesh(3, 3, 2, 7, deform="cyclic")
+    xi, _ = oracle.gll(7)
+    ora_mesh = inputs.box_mesh(3, 3, 2, xi, deform="cyclic")
+    np.testing.assert_array_equal(lib_mesh.gid, ora_mesh.gid)
+    np.testing.assert_array_equal(lib_mesh.dirichlet, ora_mesh.dirichlet)
+    for a, b in ((lib_mesh.x, ora_mesh.x), (lib_mesh.y, ora_mesh.y), (lib_mesh.z, ora_mesh.z)):
+        assert np.max(np.abs(a - b)) < 1e-15
+
+
+def test_interior_zero_and_random_fields():
+    xi, _ = oracle.gll(4)
+    m = inputs.box_mesh(2, 2, 2, xi, interior_zero=True)
+    assert np.all(m.gid[:, 1:4, 1:4, 1:4] == 0) and np.all(m.gid[:, 0] > 0)
+    f = inputs.gaussian_per_node(m.gid, 3)
+    g = m.gid.reshape(-1)
+    nz = g != 0
+    # replicated per node, independent per singleton
+    for val in np.unique(g[nz])[:50]:
+        assert np.ptp(f[g == val]) == 0.0
+    assert len(np.unique(f[~nz])) == (~nz).sum()
+    np.testing.assert_array_equal(inputs.gaussian_per_node(m.gid, 3), f)
+    u = inputs.uniform_lvector(1000, 2)
+    assert u.min() >= -1 and u.max() < 1
+    ks, a, b = inputs.fourier_modes(4, 40)
+    assert len(ks) == len(a) == len(b) and np.all(np.sum(ks ** 2, 1) <= 16)
+    # one per +- pair: no wave vector appears with its negative
+    kset = {tuple(k) for k in ks}
+    assert all(tuple(-k) not in kset for k in ks)
+    # a field of real, smooth modes: periodic on the unit cube
+    x = np.linspace(0, 1, 7)
+    v0 = inputs.fourier_field(x, 0 * x + 0.3, 0 * x + 0.6)
+    np.testing.assert_allclose(v0[0], v0[-1], atol=1e-12)
