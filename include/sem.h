@@ -161,7 +161,7 @@ typedef struct {
 
 /* Fill opts with defaults: h1 = 1, h2 = 0, k = NULL, tol = 1e-8, maxit = 1000,
  * Jacobi, check_every = 8, cheb_degree = 2, lanczos_steps = 20,
- * interval [0.1, 1.1] lambda_max, coarse_tol = 1e-2, coarse_maxit = 100,
+ * interval [0.1, 1.1] lambda_max, coarse_tol = 1e-2, coarse_maxit = 20,
  * zero_guess = 1. */
 SEM_API void sem_solve_opts_default(sem_solve_opts *opts);
 

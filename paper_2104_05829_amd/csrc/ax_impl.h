@@ -183,7 +183,13 @@ ax_kernel(int64_t E, const T *__restrict__ G, const T *__restrict__ B,
     }
 }
 
-constexpr int kAxBlocksPerCU = kAxBlocksPerCUHost;
+// workgroups per CU of the persistent grid, by variant (measured on the 16^3
+// and 32^3 boxes at N=7): FP64 Poisson 8, FP64 with the mass term 12, FP32 16
+template <typename T>
+inline int ax_blocks_per_cu(bool helm)
+{
+    return sizeof(T) == 4 ? 16 : (helm ? 12 : 8);
+}
 
 template <int NQ, typename T>
 static int ax_dispatch(const Level &L, const T *G, const T *B, const T *D, const T *u, T *w,
@@ -192,7 +198,8 @@ static int ax_dispatch(const Level &L, const T *G, const T *B, const T *D, const
 {
     using S = AxShape<NQ>;
     const int64_t groups = (L.E + S::EPB - 1) / S::EPB;
-    const int64_t cap = (int64_t)(L.n_cu > 0 ? L.n_cu : 256) * kAxBlocksPerCU;
+    const bool helm_ = h2 != 0.0;
+    const int64_t cap = (int64_t)(L.n_cu > 0 ? L.n_cu : 256) * ax_blocks_per_cu<T>(helm_);
     const int64_t nb = groups < cap ? groups : cap;
     if (nblocks) *nblocks = nb;
     if (nb == 0) return SEM_OK;

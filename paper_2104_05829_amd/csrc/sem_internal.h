@@ -30,9 +30,9 @@ void set_error(const char *fmt, ...);
     } while (0)
 
 constexpr int kMaxN = 15;
-// workgroups per CU of the persistent element-operator grid (the operator's
-// partial-sum buffer holds one value per workgroup)
-constexpr int kAxBlocksPerCUHost = 8;
+// largest number of workgroups per CU of the persistent element-operator grid
+// (the operator's partial-sum buffer holds one value per workgroup)
+constexpr int kAxMaxBlocksPerCU = 16;
 constexpr int kMaxLevels = 4;
 
 // Device scalars of one Krylov solve (kept on the device between kernels).

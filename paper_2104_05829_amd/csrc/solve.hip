@@ -496,7 +496,7 @@ static int ensure_workspace(sem_handle h, bool pmg)
         // partials: one per workgroup of the persistent operator grid
         w.n_partial = 3 * kMaxRedBlocks;
         SEM_HIP(hipMalloc(&w.partial, sizeof(double) * w.n_partial));
-        w.n_partial_ax = (int64_t)(F.n_cu > 0 ? F.n_cu : 256) * kAxBlocksPerCUHost + 64;
+        w.n_partial_ax = (int64_t)(F.n_cu > 0 ? F.n_cu : 256) * kAxMaxBlocksPerCU + 64;
         SEM_HIP(hipMalloc(&w.partial_ax, sizeof(double) * w.n_partial_ax));
         SEM_HIP(hipMalloc(&w.sc, sizeof(KrylovScalars)));
         SEM_HIP(hipMalloc(&w.sc_c, sizeof(KrylovScalars)));
@@ -1030,7 +1030,7 @@ void sem_solve_opts_default(sem_solve_opts *o)
     o->cheb_lo = 0.1;
     o->cheb_hi = 1.1;
     o->coarse_tol = 1e-2;
-    o->coarse_maxit = 100;
+    o->coarse_maxit = 20;
     o->zero_guess = 1;
 }
 

@@ -113,4 +113,5 @@ def test_default_solver_options():
     o = S.Sem.default_opts()
     assert (o.h1, o.h2, o.tol, o.maxit, o.precond, o.cheb_degree, o.lanczos_steps) == \
         (1.0, 0.0, 1e-8, 1000, S.SEM_PRECOND_JACOBI, 2, 20)
+    assert (o.coarse_tol, o.coarse_maxit) == (1e-2, 20)
     assert (o.cheb_lo, o.cheb_hi, o.zero_guess) == (0.1, 1.1, 1)
