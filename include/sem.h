@@ -59,6 +59,10 @@ enum sem_status {
 };
 
 enum sem_dtype { SEM_F64 = 0, SEM_F32 = 1 };
+
+/* Largest number of right-hand sides sem_pcg_solve_multi takes in one call
+ * (and the batch size in which sem_ax_multi / sem_gs_multi process theirs). */
+#define SEM_MAX_RHS 4
 enum sem_precond { SEM_PRECOND_JACOBI = 0, SEM_PRECOND_PMG = 1 };
 
 /*
@@ -126,6 +130,23 @@ SEM_API int sem_ax(sem_handle h, const double *u, double *w, double h1, double h
 SEM_API int sem_gs(sem_handle h, double *v, void *stream);
 
 /*
+ * Several fields through the same operator, as the three velocity components
+ * of a vector Helmholtz solve (Sec. 3.3: for velocity-oriented work the
+ * geometric factors of an element serve every component):
+ *   w_r = h1 A_L u_r + h2 B_L u_r for
+ * r = 0 .. nrhs-1, with u_r = u + r*ld and w_r = w + r*ld (device L-vectors,
+ * FP64, ld >= n_local when nrhs > 1, u and w not overlapping).  The geometric factors of an
+ * element are read once per batch of up to SEM_MAX_RHS fields.  Each w_r is
+ * bit-identical to sem_ax(u_r) with k = NULL.  nrhs >= 1.
+ */
+SEM_API int sem_ax_multi(sem_handle h, int nrhs, const double *u, double *w, int64_t ld, double h1,
+                         double h2, void *stream);
+
+/* v_r <- QQ^T v_r for v_r = v + r*ld, r = 0 .. nrhs-1 (as sem_gs, bit-identical
+ * to it per field; the maps are read once per batch of SEM_MAX_RHS fields). */
+SEM_API int sem_gs_multi(sem_handle h, int nrhs, double *v, int64_t ld, void *stream);
+
+/*
  * The same two operations at multigrid level `level` (0 = fine) in FP64 or
  * FP32; u, w, v are level-sized device L-vectors of that dtype.  FP32 is the
  * smoother precision of Sec. 3.4 (FP32 data and accumulation).
@@ -133,6 +154,13 @@ SEM_API int sem_gs(sem_handle h, double *v, void *stream);
 SEM_API int sem_ax_level(sem_handle h, int level, int dtype, const void *u, void *w, double h1, double h2,
                  void *stream);
 SEM_API int sem_gs_level(sem_handle h, int level, int dtype, void *v, void *stream);
+
+/* Batched forms at a level, as sem_ax_multi / sem_gs_multi (fields at
+ * base + r*ld, ld >= the level's n_local when nrhs > 1), in FP64 or FP32. */
+SEM_API int sem_ax_level_multi(sem_handle h, int level, int dtype, int nrhs, const void *u, void *w,
+                               int64_t ld, double h1, double h2, void *stream);
+SEM_API int sem_gs_level_multi(sem_handle h, int level, int dtype, int nrhs, void *v, int64_t ld,
+                               void *stream);
 
 typedef struct {
     double h1, h2;       /* operator h1 A(k) + h2 B (h1 = 1/Re, h2 = beta0/dt) */
@@ -182,6 +210,21 @@ SEM_API void sem_solve_opts_default(sem_solve_opts *opts);
  */
 SEM_API int sem_pcg_solve(sem_handle h, const double *b, double *x, const sem_solve_opts *opts,
                   sem_solve_stats *stats, void *stream);
+
+/*
+ * nrhs independent solves with one operator, advanced in lockstep so that
+ * every operator application and gather-scatter serves all unconverged
+ * systems at once (b_r = b + r*ld, x_r = x + r*ld, 1 <= nrhs <= SEM_MAX_RHS,
+ * ld >= n_local): the velocity Helmholtz solves of a time step (Sec. 2.2
+ * splitting; vector operator reuse of Sec. 3.3).
+ * Each system keeps its own Krylov scalars and stops at its own tolerance;
+ * with opts->k set the operator is applied field by field.  stats, if not
+ * NULL, holds nrhs records.  Returns SEM_OK when every system converged,
+ * else SEM_EBREAKDOWN if any broke down, else SEM_ENOCONV.  Synchronises
+ * `stream`.
+ */
+SEM_API int sem_pcg_solve_multi(sem_handle h, int nrhs, const double *b, double *x, int64_t ld,
+                                const sem_solve_opts *opts, sem_solve_stats *stats, void *stream);
 
 /*
  * Gradient of a loss with respect to the per-copy coefficient k of

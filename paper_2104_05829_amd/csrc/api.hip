@@ -426,6 +426,84 @@ int sem_gs_level(sem_handle h, int level, int dtype, void *v, void *stream)
     return SEM_EINVAL;
 }
 
+// batched operator / gather-scatter: nrhs fields at base + r*ld, in groups of kMaxRhs
+static int check_batch(sem_handle h, int level, int nrhs, int64_t ld, const void *a, const void *b,
+                       const char *who)
+{
+    SEM_TRY(check_level(h, level, who));
+    if (!a || !b) {
+        set_error("%s: null vector", who);
+        return SEM_EINVAL;
+    }
+    if (nrhs < 1) {
+        set_error("%s: nrhs = %d", who, nrhs);
+        return SEM_EINVAL;
+    }
+    if (nrhs > 1 && ld < h->lv[level].nL) {
+        set_error("%s: ld = %lld below n_local = %lld", who, (long long)ld, (long long)h->lv[level].nL);
+        return SEM_EINVAL;
+    }
+    return SEM_OK;
+}
+
+int sem_ax_level_multi(sem_handle h, int level, int dtype, int nrhs, const void *u, void *w, int64_t ld,
+                       double h1, double h2, void *stream)
+{
+    SEM_TRY(check_batch(h, level, nrhs, ld, u, w, "sem_ax_level_multi"));
+    const Level &L = h->lv[level];
+    if (dtype == SEM_F32 && !L.G32) {
+        set_error("sem_ax_level_multi: level %d has no FP32 operator", level);
+        return SEM_EINVAL;
+    }
+    if (dtype != SEM_F64 && dtype != SEM_F32) {
+        set_error("sem_ax_level_multi: bad dtype %d", dtype);
+        return SEM_EINVAL;
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxRhs) {
+        const VSet vs = VSet::first(std::min(kMaxRhs, nrhs - r0));
+        if (dtype == SEM_F64)
+            SEM_TRY(launch_ax_multi<double>(L, L.G, L.B, L.D, (const double *)u + r0 * ld, ld,
+                                            (double *)w + r0 * ld, ld, vs, h1, h2, nullptr, nullptr, 0,
+                                            nullptr, s, nullptr, 0));
+        else
+            SEM_TRY(launch_ax_multi<float>(L, L.G32, L.B32, L.D32, (const float *)u + r0 * ld, ld,
+                                           (float *)w + r0 * ld, ld, vs, h1, h2, nullptr, nullptr, 0,
+                                           nullptr, s, nullptr, 0));
+    }
+    return SEM_OK;
+}
+
+int sem_gs_level_multi(sem_handle h, int level, int dtype, int nrhs, void *v, int64_t ld, void *stream)
+{
+    SEM_TRY(check_batch(h, level, nrhs, ld, v, v, "sem_gs_level_multi"));
+    if (dtype != SEM_F64 && dtype != SEM_F32) {
+        set_error("sem_gs_level_multi: bad dtype %d", dtype);
+        return SEM_EINVAL;
+    }
+    const Level &L = h->lv[level];
+    const hipStream_t s = (hipStream_t)stream;
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxRhs) {
+        const VSet vs = VSet::first(std::min(kMaxRhs, nrhs - r0));
+        if (dtype == SEM_F64)
+            SEM_TRY(launch_gs_multi<double>(L, (double *)v + r0 * ld, ld, vs, s, nullptr, 0));
+        else
+            SEM_TRY(launch_gs_multi<float>(L, (float *)v + r0 * ld, ld, vs, s, nullptr, 0));
+    }
+    return SEM_OK;
+}
+
+int sem_ax_multi(sem_handle h, int nrhs, const double *u, double *w, int64_t ld, double h1, double h2,
+                 void *stream)
+{
+    return sem_ax_level_multi(h, 0, SEM_F64, nrhs, u, w, ld, h1, h2, stream);
+}
+
+int sem_gs_multi(sem_handle h, int nrhs, double *v, int64_t ld, void *stream)
+{
+    return sem_gs_level_multi(h, 0, SEM_F64, nrhs, v, ld, stream);
+}
+
 int sem_grad_k(sem_handle h, const double *u, const double *lam, double h1, double *gk, void *stream)
 {
     SEM_TRY(check_level(h, 0, "sem_grad_k"));

@@ -21,6 +21,10 @@
 #pragma once
 #include "sem_internal.h"
 
+// FMA contraction within single expressions only: the single-vector and the
+// batched kernels below then round every point identically.
+#pragma clang fp contract(on)
+
 namespace semx {
 
 template <int NQ>
@@ -191,6 +195,182 @@ inline int ax_blocks_per_cu(bool helm)
     return sizeof(T) == 4 ? 16 : (helm ? 12 : 8);
 }
 
+// Persistent grid over `groups` element groups with at most `cap`
+// workgroups: the fewest workgroups that keep the per-workgroup count
+// ceil(groups / cap), so every workgroup sweeps the same number of groups
+// (up to one) and no tail of single-group workgroups is left behind.
+inline int64_t balanced_grid(int64_t groups, int64_t cap)
+{
+    if (groups <= cap) return groups;
+    const int64_t per = (groups + cap - 1) / cap;
+    return (groups + per - 1) / per;
+}
+
+// Batched operator for nq <= 8 (an element fits one wavefront): the six
+// geometric factors (and B) of a thread's k-line are loaded into registers
+// once per element and applied to every live vector of the batch in turn, so
+// G is read once for up to kMaxRhs fields (Sec. 3.3, reuse of the geometric
+// factors across the components of a vector field).  Per point the arithmetic
+// is that of ax_kernel, in the same order.  PF: the next vector's u (or the
+// first vector of the next element) is loaded while the current one is
+// computed.  DTL: the rows of D^T come from an LDS table instead of
+// registers (fewer registers per lane, more waves per SIMD).
+template <int NQ, typename T, bool HELM, bool DOT, bool PF, bool DTL>
+__global__ void __launch_bounds__(AxShape<NQ>::THREADS)
+ax_multi_kernel(int64_t E, const T *__restrict__ G, const T *__restrict__ B,
+                const T *__restrict__ Dg, T h1, T h2, const T *__restrict__ u, int64_t ldu,
+                T *__restrict__ w, int64_t ldw, VSet vs, double *__restrict__ partial, int64_t pst,
+                const int *__restrict__ skip, int skip_stride)
+{
+    using S = AxShape<NQ>;
+    static_assert(S::ONE_WAVE, "the batched operator keeps one element group per wavefront");
+    constexpr int TPE = S::TPE, EPB = S::EPB, LD = S::LD;
+    constexpr int NP = NQ * NQ * NQ;
+    __shared__ T su[EPB][NQ][NQ][LD];
+    __shared__ T ss[EPB][NQ][NQ][LD];
+    __shared__ T sdt[DTL ? NQ : 1][NQ];  // sdt[a][b] = D[b][a]
+    __shared__ double sdot[DOT ? kMaxRhs : 1][S::THREADS];
+
+    uint32_t pack;
+    const int na = live_vectors(vs, skip, skip_stride, &pack);
+    if (na == 0) return;  // uniform over the grid
+
+    const int tid = threadIdx.x;
+    const int el = (EPB == 1) ? 0 : tid / TPE;
+    const int ij = (EPB == 1) ? tid : tid - el * TPE;
+    const int i = ij % NQ;
+    const int j = ij / NQ;
+
+    T Di[NQ], Dj[NQ], DTi[DTL ? 1 : NQ], DTj[DTL ? 1 : NQ];
+#pragma unroll
+    for (int l = 0; l < NQ; ++l) {
+        Di[l] = Dg[i * NQ + l];
+        Dj[l] = Dg[j * NQ + l];
+        if constexpr (!DTL) {
+            DTi[l] = Dg[l * NQ + i];
+            DTj[l] = Dg[l * NQ + j];
+        }
+    }
+    if constexpr (DTL)
+        if (tid < NQ * NQ) sdt[tid / NQ][tid % NQ] = Dg[(tid % NQ) * NQ + tid / NQ];
+    if constexpr (DOT)
+#pragma unroll
+        for (int q = 0; q < kMaxRhs; ++q) sdot[q][tid] = 0.0;
+    block_sync<true>();
+
+    T rn[PF ? NQ : 1];
+    int64_t g = blockIdx.x;  // element group: elements g*EPB .. g*EPB+EPB-1
+    if constexpr (PF) {
+        const int64_t e0 = g * EPB + el;
+        const int64_t v0 = pack & 255u;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) rn[k] = e0 < E ? u[v0 * ldu + e0 * NP + ij + k * TPE] : T(0);
+    }
+    for (; g * EPB < E; g += gridDim.x) {
+        const int64_t e = g * EPB + el;
+        const bool active = e < E;
+        const int64_t base = (active ? e : 0) * NP + ij;
+        T gr[NQ][6];
+        T bm[HELM ? NQ : 1];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            load_g6(G + (base + k * TPE) * 6, gr[k]);
+            if constexpr (HELM) bm[k] = B[base + k * TPE];
+        }
+#pragma unroll 1
+        for (int q = 0; q < na; ++q) {
+            const int64_t v = (pack >> (8 * q)) & 255u;
+            T ru[NQ], rw[NQ];
+            if constexpr (PF) {
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) ru[k] = rn[k];
+                const bool last = q + 1 == na;
+                const int64_t en = (last ? g + gridDim.x : g) * EPB + el;
+                if (en < E) {
+                    const int64_t vn = (pack >> (8 * (last ? 0 : q + 1))) & 255u;
+#pragma unroll
+                    for (int k = 0; k < NQ; ++k) rn[k] = u[vn * ldu + en * NP + ij + k * TPE];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) ru[k] = u[v * ldu + base + k * TPE];
+            }
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                su[el][k][j][i] = ru[k];
+                rw[k] = T(0);
+            }
+            block_sync<true>();
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                T ur = 0, us = 0, ut = 0;
+#pragma unroll
+                for (int l = 0; l < NQ; ++l) {
+                    ur += Di[l] * su[el][k][j][l];
+                    us += Dj[l] * su[el][k][l][i];
+                    ut += Dg[k * NQ + l] * ru[l];
+                }
+                const T wr = gr[k][0] * ur + gr[k][1] * us + gr[k][2] * ut;
+                const T ws = gr[k][1] * ur + gr[k][3] * us + gr[k][4] * ut;
+                const T wt = gr[k][2] * ur + gr[k][4] * us + gr[k][5] * ut;
+                su[el][k][j][i] = wr;
+                ss[el][k][j][i] = ws;
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) rw[m] += Dg[k * NQ + m] * wt;
+            }
+            block_sync<true>();
+            double dot = 0.0;
+            if constexpr (DOT) dot = sdot[q][tid];
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                T acc = rw[k];
+#pragma unroll
+                for (int l = 0; l < NQ; ++l) {
+                    T dti, dtj;
+                    if constexpr (DTL) {
+                        dti = sdt[i][l];
+                        dtj = sdt[j][l];
+                    } else {
+                        dti = DTi[l];
+                        dtj = DTj[l];
+                    }
+                    acc += dti * su[el][k][j][l];
+                    acc += dtj * ss[el][k][l][i];
+                }
+                T out = h1 * acc;
+                if constexpr (HELM) out += h2 * bm[k] * ru[k];
+                if (active) w[v * ldw + base + k * TPE] = out;
+                if constexpr (DOT)
+                    if (active) dot += (double)ru[k] * (double)out;
+            }
+            if constexpr (DOT) sdot[q][tid] = dot;
+            block_sync<true>();  // LDS is rewritten by the next vector
+        }
+    }
+
+    if constexpr (DOT) {
+        // deterministic block sums, one thread per live vector
+        __syncthreads();
+        if (tid < na) {
+            double s = 0.0;
+            for (int t = 0; t < S::THREADS; ++t) s += sdot[tid][t];
+            partial[(int64_t)((pack >> (8 * tid)) & 255u) * pst + blockIdx.x] = s;
+        }
+    }
+}
+
+// batched-operator variant and workgroups per CU of its grid (measured on
+// the 16^3 and 32^3 boxes at N=7 with three fields: prefetch on, D^T in
+// registers, 12 workgroups per CU for FP64 and FP32)
+constexpr bool kAxMultiPrefetch = true;
+constexpr bool kAxMultiDtLds = false;
+template <typename T>
+inline int ax_multi_blocks_per_cu(bool helm)
+{
+    (void)helm;
+    return 12;
+}
+
 template <int NQ, typename T>
 static int ax_dispatch(const Level &L, const T *G, const T *B, const T *D, const T *u, T *w,
                        double h1, double h2, const T *k, double *partial, int64_t *nblocks,
@@ -200,7 +380,7 @@ static int ax_dispatch(const Level &L, const T *G, const T *B, const T *D, const
     const int64_t groups = (L.E + S::EPB - 1) / S::EPB;
     const bool helm_ = h2 != 0.0;
     const int64_t cap = (int64_t)(L.n_cu > 0 ? L.n_cu : 256) * ax_blocks_per_cu<T>(helm_);
-    const int64_t nb = groups < cap ? groups : cap;
+    const int64_t nb = balanced_grid(groups, cap);
     if (nblocks) *nblocks = nb;
     if (nb == 0) return SEM_OK;
     const bool helm = h2 != 0.0;
@@ -243,6 +423,62 @@ int launch_ax(const Level &L, const T *G, const T *B, const T *D, const T *u, T 
     case 14: return ax_dispatch<14, T>(L, G, B, D, u, w, h1, h2, k, partial, nblocks, s, skip);
     case 15: return ax_dispatch<15, T>(L, G, B, D, u, w, h1, h2, k, partial, nblocks, s, skip);
     case 16: return ax_dispatch<16, T>(L, G, B, D, u, w, h1, h2, k, partial, nblocks, s, skip);
+    default: set_error("ax: unsupported order N=%d", L.N); return SEM_EINVAL;
+    }
+}
+
+template <int NQ, typename T>
+static int ax_multi_dispatch(const Level &L, const T *G, const T *B, const T *D, const T *u,
+                             int64_t ldu, T *w, int64_t ldw, const VSet &vs, double h1, double h2,
+                             double *partial, int64_t pst, int64_t *nblocks, hipStream_t s,
+                             const int *skip, int skip_stride)
+{
+    using S = AxShape<NQ>;
+    const int64_t groups = (L.E + S::EPB - 1) / S::EPB;
+    const bool helm = h2 != 0.0;
+    const int64_t cap = (int64_t)(L.n_cu > 0 ? L.n_cu : 256) * ax_multi_blocks_per_cu<T>(helm);
+    const int64_t nb = balanced_grid(groups, cap);
+    if (nblocks) *nblocks = nb;
+    if (nb == 0) return SEM_OK;
+    constexpr bool PF = kAxMultiPrefetch, DTL = kAxMultiDtLds;
+    dim3 grid((unsigned)nb), block(S::THREADS);
+#define SEM_AXM_LAUNCH(H, P)                                                                \
+    hipLaunchKernelGGL((ax_multi_kernel<NQ, T, H, P, PF, DTL>), grid, block, 0, s, L.E, G, B, \
+                       D, (T)h1, (T)h2, u, ldu, w, ldw, vs, partial, pst, skip, skip_stride)
+    if (helm) {
+        if (partial) SEM_AXM_LAUNCH(true, true); else SEM_AXM_LAUNCH(true, false);
+    } else {
+        if (partial) SEM_AXM_LAUNCH(false, true); else SEM_AXM_LAUNCH(false, false);
+    }
+#undef SEM_AXM_LAUNCH
+    SEM_HIP(hipGetLastError());
+    return SEM_OK;
+}
+
+template <typename T>
+int launch_ax_multi(const Level &L, const T *G, const T *B, const T *D, const T *u, int64_t ldu, T *w,
+                    int64_t ldw, const VSet &vs, double h1, double h2, const T *k, double *partial,
+                    int64_t pst, int64_t *nblocks, hipStream_t s, const int *skip, int skip_stride)
+{
+    if (vs.n <= 0) return SEM_OK;
+    if (vs.n == 1 || k != nullptr || L.nq > 8) {
+        // one field at a time (variable coefficient, or elements wider than a wavefront)
+        for (int q = 0; q < vs.n; ++q) {
+            const int64_t v = vs.at(q);
+            SEM_TRY(launch_ax<T>(L, G, B, D, u + v * ldu, w + v * ldw, h1, h2, k,
+                                 partial ? partial + v * pst : nullptr, nblocks, s,
+                                 skip ? skip + v * skip_stride : nullptr));
+        }
+        return SEM_OK;
+    }
+    switch (L.nq) {
+    case 2: return ax_multi_dispatch<2, T>(L, G, B, D, u, ldu, w, ldw, vs, h1, h2, partial, pst, nblocks, s, skip, skip_stride);
+    case 3: return ax_multi_dispatch<3, T>(L, G, B, D, u, ldu, w, ldw, vs, h1, h2, partial, pst, nblocks, s, skip, skip_stride);
+    case 4: return ax_multi_dispatch<4, T>(L, G, B, D, u, ldu, w, ldw, vs, h1, h2, partial, pst, nblocks, s, skip, skip_stride);
+    case 5: return ax_multi_dispatch<5, T>(L, G, B, D, u, ldu, w, ldw, vs, h1, h2, partial, pst, nblocks, s, skip, skip_stride);
+    case 6: return ax_multi_dispatch<6, T>(L, G, B, D, u, ldu, w, ldw, vs, h1, h2, partial, pst, nblocks, s, skip, skip_stride);
+    case 7: return ax_multi_dispatch<7, T>(L, G, B, D, u, ldu, w, ldw, vs, h1, h2, partial, pst, nblocks, s, skip, skip_stride);
+    case 8: return ax_multi_dispatch<8, T>(L, G, B, D, u, ldu, w, ldw, vs, h1, h2, partial, pst, nblocks, s, skip, skip_stride);
     default: set_error("ax: unsupported order N=%d", L.N); return SEM_EINVAL;
     }
 }

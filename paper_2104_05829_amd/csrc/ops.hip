@@ -28,13 +28,17 @@ __device__ inline int64_t xcd_chunk_block(int64_t b, int64_t nb)
 
 constexpr int kGsWavesPerBlock = 4;
 
+// The maps of a chunk (perm slice, segment-start mask) are loaded once and
+// applied to every vector of the batch in turn.
 template <typename T>
 __global__ void __launch_bounds__(64 * kGsWavesPerBlock)
 gs_chunk_kernel(int64_t nchunks, const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
                 const uint64_t *__restrict__ cmask, const int32_t *__restrict__ perm,
-                T *__restrict__ v, const int *__restrict__ skip)
+                T *__restrict__ v, int64_t ld, VSet vs, const int *__restrict__ skip, int skip_stride)
 {
-    if (skip != nullptr && *skip != 0) return;
+    uint32_t pack;
+    const int na = live_vectors(vs, skip, skip_stride, &pack);
+    if (na == 0) return;
     const int lane = threadIdx.x & 63;
     const int64_t c = xcd_chunk_block(blockIdx.x, gridDim.x) * kGsWavesPerBlock + (threadIdx.x >> 6);
     if (c >= nchunks) return;  // uniform per wavefront
@@ -42,7 +46,6 @@ gs_chunk_kernel(int64_t nchunks, const int32_t *__restrict__ cb, const int32_t *
     const int cnt = ce[c] - b;
     const bool act = lane < cnt;
     const int idx = act ? perm[b + lane] : 0;
-    const T val = act ? v[idx] : T(0);
     const uint64_t m = cmask[c];  // bit l: lane l starts a segment (bit 0 always set)
     const uint64_t upto = (lane == 63) ? ~0ULL : ((2ULL << lane) - 1ULL);
     const int s0 = 63 - __clzll((long long)(m & upto));      // first lane of my segment
@@ -52,51 +55,73 @@ gs_chunk_kernel(int64_t nchunks, const int32_t *__restrict__ cb, const int32_t *
     int maxlen = len;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o));
-    T acc = T(0);
-    for (int j = 0; j < maxlen; ++j) {  // wave-uniform trip count
-        const T other = __shfl(val, min(s0 + j, 63));
-        if (j < len) acc += other;
+#pragma unroll 1
+    for (int q = 0; q < na; ++q) {
+        T *vq = v + (int64_t)((pack >> (8 * q)) & 255u) * ld;
+        const T val = act ? vq[idx] : T(0);
+        T acc = T(0);
+        for (int j = 0; j < maxlen; ++j) {  // wave-uniform trip count
+            const T other = __shfl(val, min(s0 + j, 63));
+            if (j < len) acc += other;
+        }
+        if (act) vq[idx] = acc;
     }
-    if (act) v[idx] = acc;
 }
 
 // segments listed in `segs`, one thread each (copies in canonical order)
 template <typename T>
 __global__ void gs_segment_kernel(int64_t nseg, const int32_t *__restrict__ segs,
                                   const int32_t *__restrict__ perm,
-                                  const int32_t *__restrict__ offs, T *__restrict__ v,
-                                  const int *__restrict__ skip)
+                                  const int32_t *__restrict__ offs, T *__restrict__ v, int64_t ld,
+                                  VSet vs, const int *__restrict__ skip, int skip_stride)
 {
-    if (skip != nullptr && *skip != 0) return;
+    uint32_t pack;
+    const int na = live_vectors(vs, skip, skip_stride, &pack);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nseg) return;
+    if (na == 0 || t >= nseg) return;
     const int sidx = segs[t];
     const int a = offs[sidx], b = offs[sidx + 1];
-    T acc = T(0);
-    for (int o = a; o < b; ++o) acc += v[perm[o]];
-    for (int o = a; o < b; ++o) v[perm[o]] = acc;
+    for (int q = 0; q < na; ++q) {
+        T *vq = v + (int64_t)((pack >> (8 * q)) & 255u) * ld;
+        T acc = T(0);
+        for (int o = a; o < b; ++o) acc += vq[perm[o]];
+        for (int o = a; o < b; ++o) vq[perm[o]] = acc;
+    }
 }
 
 template <typename T>
-int launch_gs(const Level &L, T *v, hipStream_t s, const int *skip)
+int launch_gs_multi(const Level &L, T *v, int64_t ld, const VSet &vs, hipStream_t s,
+                    const int *skip, int skip_stride)
 {
+    if (vs.n <= 0) return SEM_OK;
     if (L.nchunks > 0) {
         const int64_t nb = (L.nchunks + kGsWavesPerBlock - 1) / kGsWavesPerBlock;
         hipLaunchKernelGGL(gs_chunk_kernel<T>, dim3((unsigned)nb), dim3(64 * kGsWavesPerBlock), 0, s,
-                           L.nchunks, L.chunk_b, L.chunk_e, L.chunk_mask, L.perm, v, skip);
+                           L.nchunks, L.chunk_b, L.chunk_e, L.chunk_mask, L.perm, v, ld, vs, skip,
+                           skip_stride);
         SEM_HIP(hipGetLastError());
     }
     if (L.nover > 0) {
         const int bs = 256;
         const int64_t nb = (L.nover + bs - 1) / bs;
         hipLaunchKernelGGL(gs_segment_kernel<T>, dim3((unsigned)nb), dim3(bs), 0, s, L.nover, L.over,
-                           L.perm, L.offs, v, skip);
+                           L.perm, L.offs, v, ld, vs, skip, skip_stride);
         SEM_HIP(hipGetLastError());
     }
     return SEM_OK;
 }
+
+template <typename T>
+int launch_gs(const Level &L, T *v, hipStream_t s, const int *skip)
+{
+    return launch_gs_multi<T>(L, v, 0, VSet::one(), s, skip, 0);
+}
 template int launch_gs<double>(const Level &, double *, hipStream_t, const int *);
 template int launch_gs<float>(const Level &, float *, hipStream_t, const int *);
+template int launch_gs_multi<double>(const Level &, double *, int64_t, const VSet &, hipStream_t,
+                                     const int *, int);
+template int launch_gs_multi<float>(const Level &, float *, int64_t, const VSet &, hipStream_t,
+                                    const int *, int);
 
 // ---------------------------------------------------------------------------
 // Geometric factors (Sec. 2.3 eqs. (grad), (vBu), (gij)): one block per

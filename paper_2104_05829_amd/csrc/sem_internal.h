@@ -34,6 +34,50 @@ constexpr int kMaxN = 15;
 // (the operator's partial-sum buffer holds one value per workgroup)
 constexpr int kAxMaxBlocksPerCU = 16;
 constexpr int kMaxLevels = 4;
+// largest number of vectors one batched operator / gather-scatter / solve
+// call processes together
+constexpr int kMaxRhs = SEM_MAX_RHS;
+
+// A batch of vectors v = idx(0) .. idx(n-1) of an array with leading
+// dimension ld (vector v starts at base + v * ld); indices packed 8 bits each.
+struct VSet {
+    int n;
+    uint32_t pack;
+    __host__ __device__ int at(int q) const { return (int)((pack >> (8 * q)) & 255u); }
+    static VSet one() { return VSet{1, 0u}; }
+    static VSet first(int n)
+    {
+        VSet v{0, 0u};
+        for (int q = 0; q < n; ++q) v.push(q);
+        return v;
+    }
+    void push(int v)
+    {
+        pack |= (uint32_t)v << (8 * n);
+        ++n;
+    }
+};
+
+// Vectors of a batch that are still to be processed: the batch's vector
+// indices minus those whose flag skip[v * skip_stride] is set, packed 8 bits
+// each into *pack; returns their number.
+__device__ inline int live_vectors(const VSet &vs, const int *skip, int skip_stride, uint32_t *pack)
+{
+    int na = 0;
+    uint32_t pk = 0;
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q) {
+        if (q < vs.n) {
+            const int v = vs.at(q);
+            if (skip == nullptr || skip[(int64_t)v * skip_stride] == 0) {
+                pk |= (uint32_t)v << (8 * na);
+                ++na;
+            }
+        }
+    }
+    *pack = pk;
+    return na;
+}
 
 // Device scalars of one Krylov solve (kept on the device between kernels).
 struct KrylovScalars {
@@ -88,18 +132,21 @@ struct Level {
 
 struct Workspace {
     int64_t nL = 0;
-    // FP64 outer vectors
+    int nv = 0;        // vectors per array (batched solves), grown on demand
+    bool pmg = false;  // multigrid vectors allocated
+    // FP64 outer vectors, [nv][nL]
     double *r = nullptr, *p = nullptr, *w = nullptr, *z = nullptr;
     double *aux = nullptr;  // adjoint right-hand side
-    // reduction partials and scalars
+    // reduction partials (vector v at + v * pst) and scalars (one per vector)
     double *partial = nullptr;     // vector-kernel partial sums
-    int64_t n_partial = 0;
+    int64_t pst = 0;
     double *partial_ax = nullptr;  // operator-kernel partial sums of (p, A_L p)
-    int64_t n_partial_ax = 0;
-    KrylovScalars *sc = nullptr;      // outer
-    KrylovScalars *sc_c = nullptr;    // coarse
-    KrylovScalars *host_sc = nullptr; // pinned mirror
-    // multigrid per-level vectors (FP32 on smoother levels, FP64 on the coarsest)
+    int64_t pst_ax = 0;
+    KrylovScalars *sc = nullptr;      // outer [kMaxRhs]
+    KrylovScalars *sc_c = nullptr;    // coarse [kMaxRhs]
+    KrylovScalars *host_sc = nullptr; // pinned mirror: outer, then coarse
+    // multigrid per-level vectors [nv][nL of the level] (FP32 on smoother
+    // levels, FP64 on the coarsest)
     void *mg_r[kMaxLevels] = {}, *mg_x[kMaxLevels] = {}, *mg_t[kMaxLevels] = {},
          *mg_d[kMaxLevels] = {}, *mg_s[kMaxLevels] = {};
     double *c_r = nullptr, *c_p = nullptr, *c_w = nullptr;  // coarse CG
@@ -140,6 +187,20 @@ int launch_ax(const Level &L, const T *G, const T *B, const T *D, const T *u, T 
 template <typename T>
 int launch_gs(const Level &L, T *v, hipStream_t s, const int *skip = nullptr);
 
+// Batched forms: the vectors of `vs` (vector v at u + v * ldu, w + v * ldw),
+// one launch for the whole batch; the element operator reads each element's
+// geometric factors once for all vectors.  skip (nullable) + v * skip_stride
+// is vector v's flag: vectors flagged at launch time are left untouched.
+// Operator partial sums of u_v.w_v go to partial[v * pst + block].
+template <typename T>
+int launch_ax_multi(const Level &L, const T *G, const T *B, const T *D, const T *u, int64_t ldu, T *w,
+                    int64_t ldw, const VSet &vs, double h1, double h2, const T *k, double *partial,
+                    int64_t pst, int64_t *nblocks, hipStream_t s, const int *skip, int skip_stride);
+
+template <typename T>
+int launch_gs_multi(const Level &L, T *v, int64_t ld, const VSet &vs, hipStream_t s,
+                    const int *skip, int skip_stride);
+
 int launch_geometry(const Level &L, const double *x, const double *y, const double *z,
                     double *G, double *B, int *bad, hipStream_t s);
 
@@ -163,8 +224,8 @@ int host_gll(int N, double *xi, double *rho, double *D);
 void host_interp(int ns, const double *xs, int nt, const double *xt, double *J);
 
 // solver entry (solve.hip)
-int pcg_solve(sem_handle h, const double *b, double *x, const sem_solve_opts *o,
-              sem_solve_stats *st, hipStream_t s);
+int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld,
+              const sem_solve_opts *o, sem_solve_stats *st, hipStream_t s);
 void free_workspace(sem_handle h);
 
 }  // namespace semx

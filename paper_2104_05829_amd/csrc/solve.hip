@@ -73,36 +73,45 @@ __device__ inline void sum_partials(const double *partial, int64_t nb, double (&
 }
 
 // ------------------------------------------------------------------ vectors
-template <typename T>
-__global__ void fill_kernel(int64_t n, T *v, T val)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+// Kernels over a batch of vectors take the batch `vs` and the leading
+// dimension of each array; grid.y runs over the vectors of the batch, and
+// vector v's Krylov scalars and partial sums are sc[v] and partial + v * pst.
+__device__ inline int64_t vsel(const VSet &vs) { return vs.at(blockIdx.y); }
+
+#define GRID_LOOP(i, n)                                                                    \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n);              \
          i += (int64_t)gridDim.x * blockDim.x)
-        v[i] = val;
+
+template <typename T>
+__global__ void fill_kernel(int64_t n, VSet vs, int64_t ld, T *v, T val)
+{
+    T *q = v + vsel(vs) * ld;
+    GRID_LOOP(i, n) q[i] = val;
 }
 
 template <typename T, typename TW>
-__global__ void mask_kernel(int64_t n, const TW *__restrict__ W, T *__restrict__ v)
+__global__ void mask_kernel(int64_t n, VSet vs, int64_t ld, const TW *__restrict__ W, T *__restrict__ v)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        if (!(W[i] > TW(0))) v[i] = T(0);
+    T *q = v + vsel(vs) * ld;
+    GRID_LOOP(i, n)
+        if (!(W[i] > TW(0))) q[i] = T(0);
 }
 
 template <typename TA, typename TB>
-__global__ void convert_kernel(int64_t n, const TA *__restrict__ a, TB *__restrict__ b)
+__global__ void convert_kernel(int64_t n, VSet vs, int64_t lda, const TA *__restrict__ a, int64_t ldb,
+                               TB *__restrict__ b)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        b[i] = (TB)a[i];
+    const int64_t v = vsel(vs);
+    const TA *pa = a + v * lda;
+    TB *pb = b + v * ldb;
+    GRID_LOOP(i, n) pb[i] = (TB)pa[i];
 }
 
 __global__ void invert_diag_kernel(int64_t n, const double *__restrict__ W,
                                    const double *__restrict__ d, double *__restrict__ Dinv,
                                    float *__restrict__ Dinv32)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    GRID_LOOP(i, n) {
         const double v = (W[i] > 0.0 && d[i] != 0.0) ? 1.0 / d[i] : 0.0;
         Dinv[i] = v;
         if (Dinv32) Dinv32[i] = (float)v;
@@ -114,22 +123,25 @@ __global__ void dot_kernel(int64_t n, const double *__restrict__ W, const double
                            const double *__restrict__ b, double *__restrict__ partial)
 {
     double s[1] = {0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        s[0] += W[i] * a[i] * b[i];
+    GRID_LOOP(i, n) s[0] += W[i] * a[i] * b[i];
     block_sum_store<1>(s, partial);
 }
 
 // ---------------------------------------------------------------- Jacobi-PCG
 // r = b - Ax (Ax may be null: x = 0), p = Dinv r; partials (W r p, W r r, W b b)
-__global__ void pcg_init_kernel(int64_t n, const double *__restrict__ b, const double *__restrict__ Ax,
+__global__ void pcg_init_kernel(int64_t n, VSet vs, int64_t ldb, const double *__restrict__ b,
+                                int64_t ld, const double *__restrict__ Ax,
                                 const double *__restrict__ Dinv, const double *__restrict__ W,
                                 double *__restrict__ r, double *__restrict__ p,
-                                double *__restrict__ partial, int precondition)
+                                double *__restrict__ partial, int64_t pst, int precondition)
 {
+    const int64_t v = vsel(vs);
+    b += v * ldb;
+    if (Ax) Ax += v * ld;
+    r += v * ld;
+    if (p) p += v * ld;
     double s[3] = {0.0, 0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    GRID_LOOP(i, n) {
         const double ri = b[i] - (Ax ? Ax[i] : 0.0);
         r[i] = ri;
         const double zi = precondition ? Dinv[i] * ri : ri;
@@ -139,14 +151,17 @@ __global__ void pcg_init_kernel(int64_t n, const double *__restrict__ b, const d
         s[1] += wi * ri * ri;
         s[2] += wi * b[i] * b[i];
     }
-    block_sum_store<3>(s, partial);
+    block_sum_store<3>(s, partial + v * pst);
 }
 
-__global__ void fin_init_kernel(const double *partial, int64_t nb, KrylovScalars *sc, double tol,
-                                int maxit)
+// one block per vector
+__global__ void fin_init_kernel(VSet vs, const double *partial, int64_t pst, int64_t nb,
+                                KrylovScalars *sc, double tol, int maxit)
 {
+    const int64_t v = vsel(vs);
+    sc += v;
     double res[3];
-    sum_partials<3>(partial, nb, res);
+    sum_partials<3>(partial + v * pst, nb, res);
     if (threadIdx.x == 0) {
         sc->rz = res[0];
         sc->rz_old = res[0];
@@ -166,43 +181,28 @@ __global__ void fin_init_kernel(const double *partial, int64_t nb, KrylovScalars
 }
 
 // ------------------------------------------------- fused Krylov iterations
-// QQ^T value of copy l.  With segid == nullptr, w is already assembled (a
-// gs_kernel pass ran before); otherwise the sum over the copies of its node is
-// taken on the fly in the canonical order, starting from 0 (bit-identical to
-// gs_kernel's).  The on-the-fly form trades the gs pass for dependent
-// scattered loads and is only worth it for tiny levels.
-template <typename T>
-__device__ inline T assembled_value(const T *__restrict__ w, int64_t l,
-                                    const int32_t *__restrict__ segid,
-                                    const int32_t *__restrict__ perm,
-                                    const int32_t *__restrict__ offs)
-{
-    if (segid == nullptr) return w[l];
-    const int sg = segid[l];
-    if (sg < 0) return w[l];
-    const int a = offs[sg], b = offs[sg + 1];
-    T acc = T(0);
-    for (int o = a; o < b; ++o) acc += w[perm[o]];
-    return acc;
-}
-
 // Jacobi-PCG update.  Every block sums the operator kernel's partials of
 // (p, A_L p) in the same fixed order, so all blocks hold the same alpha;
-// x += alpha p; r -= alpha QQ^T(A_L p); partials (W r Dinv r, W r r).
-// rz2[parity] is the current (r, z).
-__global__ void pcg_update_fused_kernel(int64_t n, KrylovScalars *sc, int parity,
-                                        const double *__restrict__ pax, int64_t nbax,
+// x += alpha p; r -= alpha QQ^T(A_L p) (w already assembled); partials
+// (W r Dinv r, W r r).  rz2[parity] is the current (r, z).
+__global__ void pcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t ldx,
+                                        KrylovScalars *sc, int parity,
+                                        const double *__restrict__ pax, int64_t pst_ax, int64_t nbax,
                                         const double *__restrict__ p, const double *__restrict__ w,
-                                        const int32_t *__restrict__ segid,
-                                        const int32_t *__restrict__ perm,
-                                        const int32_t *__restrict__ offs,
                                         const double *__restrict__ Dinv,
                                         const double *__restrict__ W, double *__restrict__ x,
-                                        double *__restrict__ r, double *__restrict__ partial)
+                                        double *__restrict__ r, double *__restrict__ partial,
+                                        int64_t pst)
 {
+    const int64_t v = vsel(vs);
+    sc += v;
     if (sc->done) return;
+    p += v * ld;
+    w += v * ld;
+    r += v * ld;
+    x += v * ldx;
     double res[1];
-    sum_partials<1>(pax, nbax, res);
+    sum_partials<1>(pax + v * pst_ax, nbax, res);
     const double pw = res[0];
     if (!(pw > 0.0) || !isfinite(pw)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -218,29 +218,32 @@ __global__ void pcg_update_fused_kernel(int64_t n, KrylovScalars *sc, int parity
         sc->alpha = a;
     }
     double s[2] = {0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    GRID_LOOP(i, n) {
         x[i] += a * p[i];
-        const double ri = r[i] - a * assembled_value(w, i, segid, perm, offs);
+        const double ri = r[i] - a * w[i];
         r[i] = ri;
         const double wr = W[i] * ri;
         s[0] += wr * Dinv[i] * ri;
         s[1] += wr * ri;
     }
-    block_sum_store<2>(s, partial);
+    block_sum_store<2>(s, partial + v * pst);
 }
 
 // Jacobi-PCG direction update with beta and the convergence decision taken
 // by every block from the update's partials (identical in all blocks);
 // block 0 records them.  `iter` is the 1-based number of this iteration.
-__global__ void pcg_p_fused_kernel(int64_t n, KrylovScalars *sc, int parity, int iter,
-                                   const double *__restrict__ pu, int64_t nbu,
+__global__ void pcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars *sc, int parity,
+                                   int iter, const double *__restrict__ pu, int64_t pst, int64_t nbu,
                                    const double *__restrict__ Dinv, const double *__restrict__ r,
                                    double *__restrict__ p)
 {
+    const int64_t v = vsel(vs);
+    sc += v;
     if (sc->done) return;
+    r += v * ld;
+    p += v * ld;
     double res[2];
-    sum_partials<2>(pu, nbu, res);
+    sum_partials<2>(pu + v * pst, nbu, res);
     const double rz = res[0], rr = res[1];
     const bool bad = !isfinite(rz) || !isfinite(rr);
     const bool stop = bad || rr <= sc->tol2 || iter >= sc->maxit;
@@ -254,25 +257,28 @@ __global__ void pcg_p_fused_kernel(int64_t n, KrylovScalars *sc, int parity, int
     }
     if (stop) return;
     const double be = rz / sc->rz2[parity];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = Dinv[i] * r[i] + be * p[i];
+    GRID_LOOP(i, n) p[i] = Dinv[i] * r[i] + be * p[i];
 }
 
 // flexible-CG update: alpha from the operator partials, x += alpha p,
 // r -= alpha QQ^T(A_L p); partial (W r r)
-__global__ void fcg_update_fused_kernel(int64_t n, KrylovScalars *sc, int parity,
-                                        const double *__restrict__ pax, int64_t nbax,
+__global__ void fcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t ldx,
+                                        KrylovScalars *sc, int parity,
+                                        const double *__restrict__ pax, int64_t pst_ax, int64_t nbax,
                                         const double *__restrict__ p, const double *__restrict__ w,
-                                        const int32_t *__restrict__ segid,
-                                        const int32_t *__restrict__ perm,
-                                        const int32_t *__restrict__ offs,
                                         const double *__restrict__ W, double *__restrict__ x,
-                                        double *__restrict__ r, double *__restrict__ partial)
+                                        double *__restrict__ r, double *__restrict__ partial,
+                                        int64_t pst)
 {
+    const int64_t v = vsel(vs);
+    sc += v;
     if (sc->done) return;
+    p += v * ld;
+    w += v * ld;
+    r += v * ld;
+    x += v * ldx;
     double res[1];
-    sum_partials<1>(pax, nbax, res);
+    sum_partials<1>(pax + v * pst_ax, nbax, res);
     const double pw = res[0];
     if (!(pw > 0.0) || !isfinite(pw)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -288,42 +294,49 @@ __global__ void fcg_update_fused_kernel(int64_t n, KrylovScalars *sc, int parity
         sc->alpha = a;
     }
     double s[1] = {0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    GRID_LOOP(i, n) {
         x[i] += a * p[i];
-        const double ri = r[i] - a * assembled_value(w, i, segid, perm, offs);
+        const double ri = r[i] - a * w[i];
         r[i] = ri;
         s[0] += W[i] * ri * ri;
     }
-    block_sum_store<1>(s, partial);
+    block_sum_store<1>(s, partial + v * pst);
 }
 
 // (z, w)_W and (z, r)_W for assembled w
-__global__ void dot_zw_kernel(int64_t n, const KrylovScalars *sc, const double *__restrict__ W,
-                              const double *__restrict__ z, const double *__restrict__ wa,
-                              const double *__restrict__ r, double *__restrict__ partial)
+__global__ void dot_zw_kernel(int64_t n, VSet vs, int64_t ld, const KrylovScalars *sc,
+                              const double *__restrict__ W, const double *__restrict__ z,
+                              const double *__restrict__ wa, const double *__restrict__ r,
+                              double *__restrict__ partial, int64_t pst)
 {
-    if (sc->done) return;
+    const int64_t v = vsel(vs);
+    if (sc[v].done) return;
+    z += v * ld;
+    wa += v * ld;
+    r += v * ld;
     double s[2] = {0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    GRID_LOOP(i, n) {
         const double wz = W[i] * z[i];
         s[0] += wz * wa[i];
         s[1] += wz * r[i];
     }
-    block_sum_store<2>(s, partial);
+    block_sum_store<2>(s, partial + v * pst);
 }
 
 // Polak-Ribiere direction update, beta = (z_new, r_new - r_old) / (z_old, r_old)
 // = -alpha (z_new, A p) / rz_old (r_new - r_old = -alpha A p), taken by every
 // block from the partials of dot_zw_kernel; first = 1 gives p = z.
-__global__ void fcg_p_fused_kernel(int64_t n, KrylovScalars *sc, int parity,
-                                   const double *__restrict__ pz, int64_t nbz,
+__global__ void fcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars *sc, int parity,
+                                   const double *__restrict__ pz, int64_t pst, int64_t nbz,
                                    const double *__restrict__ z, double *__restrict__ p, int first)
 {
+    const int64_t v = vsel(vs);
+    sc += v;
     if (sc->done) return;
+    z += v * ld;
+    p += v * ld;
     double res[2];
-    sum_partials<2>(pz, nbz, res);
+    sum_partials<2>(pz + v * pst, nbz, res);
     const double zw = res[0], zr = res[1];
     const double be = first ? 0.0 : -sc->alpha * zw / sc->rz2[parity];
     const bool bad = !isfinite(be) || !isfinite(zr);
@@ -338,48 +351,51 @@ __global__ void fcg_p_fused_kernel(int64_t n, KrylovScalars *sc, int parity,
         }
     }
     if (bad) return;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = z[i] + be * p[i];
+    GRID_LOOP(i, n) p[i] = z[i] + be * p[i];
 }
 
-// Chebyshev step with QQ^T of the operator output taken on the fly:
-// res = r - QQ^T t (t = A_L x, or absent when x = 0),
-// d = c1 d + c2 Dinv res, x += d (x = d when `init`)
-__global__ void cheb_fused_kernel(int64_t n, const float *__restrict__ r, const float *__restrict__ t,
-                                  const int32_t *__restrict__ segid, const int32_t *__restrict__ perm,
-                                  const int32_t *__restrict__ offs, const float *__restrict__ Dinv,
+// Chebyshev step on assembled t = QQ^T A_L x (t null when x = 0):
+// res = r - t, d = c1 d + c2 Dinv res, x += d (x = d when `init`)
+__global__ void cheb_fused_kernel(int64_t n, VSet vs, int64_t ld, const float *__restrict__ r,
+                                  const float *__restrict__ t, const float *__restrict__ Dinv,
                                   float *__restrict__ d, float *__restrict__ x, float c1, float c2,
                                   int init)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const float res = t ? r[i] - assembled_value(t, i, segid, perm, offs) : r[i];
+    const int64_t v = vsel(vs);
+    r += v * ld;
+    if (t) t += v * ld;
+    d += v * ld;
+    x += v * ld;
+    GRID_LOOP(i, n) {
+        const float res = t ? r[i] - t[i] : r[i];
         const float di = (init ? 0.0f : c1 * d[i]) + c2 * Dinv[i] * res;
         d[i] = di;
         x[i] = init ? di : x[i] + di;
     }
 }
 
-// s = W (r - QQ^T t)
-__global__ void wresid_fused_kernel(int64_t n, const float *__restrict__ W,
+// s = W (r - t) for assembled t
+__global__ void wresid_fused_kernel(int64_t n, VSet vs, int64_t ld, const float *__restrict__ W,
                                     const float *__restrict__ r, const float *__restrict__ t,
-                                    const int32_t *__restrict__ segid,
-                                    const int32_t *__restrict__ perm,
-                                    const int32_t *__restrict__ offs, float *__restrict__ s)
+                                    float *__restrict__ s)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        s[i] = W[i] * (r[i] - assembled_value(t, i, segid, perm, offs));
+    const int64_t v = vsel(vs);
+    r += v * ld;
+    t += v * ld;
+    s += v * ld;
+    GRID_LOOP(i, n) s[i] = W[i] * (r[i] - t[i]);
 }
 
-// flexible CG convergence decision after the update (one block): iteration
-// count, (r, r)_W, done
-__global__ void fin_conv_kernel(const double *partial, int64_t nb, KrylovScalars *sc)
+// flexible CG convergence decision after the update (one block per vector):
+// iteration count, (r, r)_W, done
+__global__ void fin_conv_kernel(VSet vs, const double *partial, int64_t pst, int64_t nb,
+                                KrylovScalars *sc)
 {
+    const int64_t v = vsel(vs);
+    sc += v;
     if (sc->done) return;
     double res[1];
-    sum_partials<1>(partial, nb, res);
+    sum_partials<1>(partial + v * pst, nb, res);
     if (threadIdx.x == 0) {
         sc->iters += 1;
         sc->rr = res[0];
@@ -394,11 +410,12 @@ __global__ void fin_conv_kernel(const double *partial, int64_t nb, KrylovScalars
 
 // y += a (prolongation added to the smoothed iterate)
 template <typename T>
-__global__ void add_kernel(int64_t n, const T *__restrict__ a, T *__restrict__ y)
+__global__ void add_kernel(int64_t n, VSet vs, int64_t ld, const T *__restrict__ a, T *__restrict__ y)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        y[i] += a[i];
+    const int64_t v = vsel(vs);
+    a += v * ld;
+    y += v * ld;
+    GRID_LOOP(i, n) y[i] += a[i];
 }
 
 // ---------------------------------------------------------- load / adjoint
@@ -453,24 +470,47 @@ __global__ void axpby_kernel(int64_t n, const double *__restrict__ x, double a, 
         hipLaunchKernelGGL(kern, dim3(red_grid(n)), dim3(kRB), 0, s, __VA_ARGS__);          \
         SEM_HIP(hipGetLastError());                                                         \
     } while (0)
-#define LAUNCH_1(kern, s, ...)                                                              \
+// one grid row per vector of the batch vs
+#define LAUNCH_B(kern, len_, vs_, s_, ...)                                                  \
     do {                                                                                    \
-        hipLaunchKernelGGL(kern, dim3(1), dim3(kRB), 0, s, __VA_ARGS__);                    \
+        hipLaunchKernelGGL(kern, dim3(red_grid(len_), (unsigned)(vs_).n), dim3(kRB), 0, s_, \
+                           __VA_ARGS__);                                                    \
         SEM_HIP(hipGetLastError());                                                         \
     } while (0)
+#define LAUNCH_1B(kern, vs_, s_, ...)                                                       \
+    do {                                                                                    \
+        hipLaunchKernelGGL(kern, dim3(1, (unsigned)(vs_).n), dim3(kRB), 0, s_, __VA_ARGS__); \
+        SEM_HIP(hipGetLastError());                                                         \
+    } while (0)
+
+// stride, in ints, between the `done` flags of consecutive KrylovScalars
+constexpr int kScStride = (int)(sizeof(KrylovScalars) / sizeof(int));
+static_assert(sizeof(KrylovScalars) % sizeof(int) == 0, "KrylovScalars size");
+
+static void free_vectors(Workspace &w)
+{
+    void *ptrs[] = {w.r, w.p, w.w, w.z, w.c_r, w.c_p, w.c_w};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    w.r = w.p = w.w = w.z = w.c_r = w.c_p = w.c_w = nullptr;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        void **q[] = {&w.mg_r[l], &w.mg_x[l], &w.mg_t[l], &w.mg_d[l], &w.mg_s[l]};
+        for (void **p : q) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+    }
+    w.nv = 0;
+    w.pmg = false;
+}
 
 void free_workspace(sem_handle h)
 {
     Workspace &w = h->ws;
-    void *ptrs[] = {w.r, w.p, w.w, w.z, w.aux, w.partial, w.partial_ax, w.sc, w.sc_c, w.c_r,
-                    w.c_p, w.c_w};
+    free_vectors(w);
+    void *ptrs[] = {w.aux, w.partial, w.partial_ax, w.sc, w.sc_c};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    for (int l = 0; l < kMaxLevels; ++l) {
-        void *q[] = {w.mg_r[l], w.mg_x[l], w.mg_t[l], w.mg_d[l], w.mg_s[l]};
-        for (void *p : q)
-            if (p) (void)hipFree(p);
-    }
     if (w.host_sc) (void)hipHostFree(w.host_sc);
     h->ws = Workspace{};
     for (int l = 0; l < kMaxLevels; ++l) {
@@ -482,47 +522,57 @@ void free_workspace(sem_handle h)
     h->key = PrecondKey{};
 }
 
-static int ensure_workspace(sem_handle h, bool pmg)
+// workspace for batches of up to nv vectors (grown, never shrunk)
+static int ensure_workspace(sem_handle h, bool pmg, int nv)
 {
     Workspace &w = h->ws;
     const Level &F = h->lv[0];
-    if (!w.r) {
+    if (!w.sc) {
         w.nL = F.nL;
-        SEM_HIP(hipMalloc(&w.r, sizeof(double) * F.nL));
-        SEM_HIP(hipMalloc(&w.p, sizeof(double) * F.nL));
-        SEM_HIP(hipMalloc(&w.w, sizeof(double) * F.nL));
-        SEM_HIP(hipMalloc(&w.z, sizeof(double) * F.nL));
-        // vector-kernel partials: at most kMaxRedBlocks records of 3; operator
-        // partials: one per workgroup of the persistent operator grid
-        w.n_partial = 3 * kMaxRedBlocks;
-        SEM_HIP(hipMalloc(&w.partial, sizeof(double) * w.n_partial));
-        w.n_partial_ax = (int64_t)(F.n_cu > 0 ? F.n_cu : 256) * kAxMaxBlocksPerCU + 64;
-        SEM_HIP(hipMalloc(&w.partial_ax, sizeof(double) * w.n_partial_ax));
-        SEM_HIP(hipMalloc(&w.sc, sizeof(KrylovScalars)));
-        SEM_HIP(hipMalloc(&w.sc_c, sizeof(KrylovScalars)));
-        SEM_HIP(hipHostMalloc((void **)&w.host_sc, 2 * sizeof(KrylovScalars), hipHostMallocDefault));
+        // vector-kernel partials: at most kMaxRedBlocks records of 3 per
+        // vector; operator partials: one per workgroup of the persistent grid
+        w.pst = 3 * kMaxRedBlocks;
+        SEM_HIP(hipMalloc(&w.partial, sizeof(double) * w.pst * kMaxRhs));
+        w.pst_ax = (int64_t)(F.n_cu > 0 ? F.n_cu : 256) * kAxMaxBlocksPerCU + 64;
+        SEM_HIP(hipMalloc(&w.partial_ax, sizeof(double) * w.pst_ax * kMaxRhs));
+        SEM_HIP(hipMalloc(&w.sc, sizeof(KrylovScalars) * kMaxRhs));
+        SEM_HIP(hipMalloc(&w.sc_c, sizeof(KrylovScalars) * kMaxRhs));
+        SEM_HIP(hipHostMalloc((void **)&w.host_sc, 2 * kMaxRhs * sizeof(KrylovScalars),
+                              hipHostMallocDefault));
+    }
+    if (w.nv < nv || (pmg && !w.pmg)) {
+        const int nvn = std::max(nv, w.nv);
+        const bool pm = pmg || w.pmg;
+        free_vectors(w);
+        const int64_t n = F.nL;
+        SEM_HIP(hipMalloc(&w.r, sizeof(double) * n * nvn));
+        SEM_HIP(hipMalloc(&w.p, sizeof(double) * n * nvn));
+        SEM_HIP(hipMalloc(&w.w, sizeof(double) * n * nvn));
+        SEM_HIP(hipMalloc(&w.z, sizeof(double) * n * nvn));
+        if (pm) {
+            for (int l = 0; l + 1 < h->n_levels; ++l) {
+                const int64_t m = h->lv[l].nL * nvn;
+                SEM_HIP(hipMalloc(&w.mg_r[l], sizeof(float) * m));
+                SEM_HIP(hipMalloc(&w.mg_x[l], sizeof(float) * m));
+                SEM_HIP(hipMalloc(&w.mg_t[l], sizeof(float) * m));
+                SEM_HIP(hipMalloc(&w.mg_d[l], sizeof(float) * m));
+                SEM_HIP(hipMalloc(&w.mg_s[l], sizeof(float) * m));
+            }
+            const int lc = h->n_levels - 1;
+            const int64_t m = h->lv[lc].nL * nvn;
+            SEM_HIP(hipMalloc(&w.mg_r[lc], sizeof(double) * m));  // coarse rhs
+            SEM_HIP(hipMalloc(&w.mg_x[lc], sizeof(double) * m));  // coarse solution
+            SEM_HIP(hipMalloc(&w.c_r, sizeof(double) * m));
+            SEM_HIP(hipMalloc(&w.c_p, sizeof(double) * m));
+            SEM_HIP(hipMalloc(&w.c_w, sizeof(double) * m));
+        }
+        w.nv = nvn;
+        w.pmg = pm;
     }
     for (int l = 0; l < h->n_levels; ++l) {
         Level &L = h->lv[l];
         if (!L.Dinv) SEM_HIP(hipMalloc(&L.Dinv, sizeof(double) * L.nL));
         if (pmg && l < h->n_levels - 1 && !L.Dinv32) SEM_HIP(hipMalloc(&L.Dinv32, sizeof(float) * L.nL));
-    }
-    if (pmg && !w.c_r) {
-        for (int l = 0; l + 1 < h->n_levels; ++l) {
-            const int64_t n = h->lv[l].nL;
-            SEM_HIP(hipMalloc(&w.mg_r[l], sizeof(float) * n));
-            SEM_HIP(hipMalloc(&w.mg_x[l], sizeof(float) * n));
-            SEM_HIP(hipMalloc(&w.mg_t[l], sizeof(float) * n));
-            SEM_HIP(hipMalloc(&w.mg_d[l], sizeof(float) * n));
-            SEM_HIP(hipMalloc(&w.mg_s[l], sizeof(float) * n));
-        }
-        const int lc = h->n_levels - 1;
-        const int64_t n = h->lv[lc].nL;
-        SEM_HIP(hipMalloc(&w.mg_r[lc], sizeof(double) * n));  // coarse rhs
-        SEM_HIP(hipMalloc(&w.mg_x[lc], sizeof(double) * n));  // coarse solution
-        SEM_HIP(hipMalloc(&w.c_r, sizeof(double) * n));
-        SEM_HIP(hipMalloc(&w.c_p, sizeof(double) * n));
-        SEM_HIP(hipMalloc(&w.c_w, sizeof(double) * n));
     }
     return SEM_OK;
 }
@@ -593,6 +643,7 @@ static int lanczos_lmax(sem_handle h, int l, double h1, double h2, int steps, do
     Level &L = h->lv[l];
     Workspace &w = h->ws;
     const int64_t n = L.nL;
+    const VSet one = VSet::one();
     double *v = w.r, *vp = w.p, *t = w.w, *u = w.z;
     LAUNCH_V(splitmix_kernel, n, s, n, L.gid, L.W, h->lanczos_seed, v);
     double nrm2 = 0.0;
@@ -602,7 +653,7 @@ static int lanczos_lmax(sem_handle h, int l, double h1, double h2, int steps, do
         return SEM_OK;
     }
     LAUNCH_V(axpby_kernel, n, s, n, v, 1.0 / std::sqrt(nrm2), 0.0, v);
-    LAUNCH_V(fill_kernel<double>, n, s, n, vp, 0.0);
+    LAUNCH_B(fill_kernel<double>, n, one, s, n, one, (int64_t)0, vp, 0.0);
     std::vector<double> al, be;
     double beta = 0.0;
     for (int it = 0; it < steps; ++it) {
@@ -610,7 +661,7 @@ static int lanczos_lmax(sem_handle h, int l, double h1, double h2, int steps, do
         LAUNCH_V(sqrtd_axpby_kernel, n, s, n, L.Dinv, v, 1.0, 0.0, t);
         SEM_TRY(launch_ax<double>(L, L.G, L.B, L.D, t, u, h1, h2, nullptr, nullptr, nullptr, s));
         SEM_TRY(launch_gs<double>(L, u, s));
-        LAUNCH_V((mask_kernel<double, double>), n, s, n, L.W, u);
+        LAUNCH_B((mask_kernel<double, double>), n, one, s, n, one, (int64_t)0, L.W, u);
         LAUNCH_V(sqrtd_axpby_kernel, n, s, n, L.Dinv, u, 1.0, 0.0, t);  // t = S A S v
         LAUNCH_V(axpby_kernel, n, s, n, vp, -beta, 1.0, t);              // t -= beta vp
         double alpha = 0.0;
@@ -631,22 +682,22 @@ static int lanczos_lmax(sem_handle h, int l, double h1, double h2, int steps, do
     return SEM_OK;
 }
 
-struct ChebCoef {
-    double theta, delta;
-};
-
-// FP32 operator on a smoother level: t = QQ^T A_L x (Dirichlet copies of t are
-// ignored by the consumers, whose Dinv and W vanish there)
-static int apply_f32(const Level &L, const float *x, float *t, double h1, double h2, hipStream_t s)
+// FP32 operator on a smoother level for the batch vs (arrays [nv][nL]):
+// t = QQ^T A_L x (Dirichlet copies of t are ignored by the consumers, whose
+// Dinv and W vanish there)
+static int apply_f32(const Level &L, const VSet &vs, const float *x, float *t, double h1, double h2,
+                     hipStream_t s)
 {
-    SEM_TRY(launch_ax<float>(L, L.G32, L.B32, L.D32, x, t, h1, h2, nullptr, nullptr, nullptr, s));
-    return launch_gs<float>(L, t, s);
+    SEM_TRY(launch_ax_multi<float>(L, L.G32, L.B32, L.D32, x, L.nL, t, L.nL, vs, h1, h2, nullptr,
+                                   nullptr, 0, nullptr, s, nullptr, 0));
+    return launch_gs_multi<float>(L, t, L.nL, vs, s, nullptr, 0);
 }
 
 // Chebyshev-accelerated Jacobi (Saad, Iterative Methods, Alg. 12.1, applied to
 // Dinv A x = Dinv r) with `deg` updates; x == 0 on entry when `zero`.
-static int chebyshev(const Level &L, int l, sem_handle h, const float *r, float *x, bool zero,
-                     double lmin, double lmax, int deg, double h1, double h2, hipStream_t s)
+static int chebyshev(const Level &L, int l, sem_handle h, const VSet &vs, const float *r, float *x,
+                     bool zero, double lmin, double lmax, int deg, double h1, double h2,
+                     hipStream_t s)
 {
     Workspace &w = h->ws;
     float *t = (float *)w.mg_t[l], *d = (float *)w.mg_d[l];
@@ -655,18 +706,18 @@ static int chebyshev(const Level &L, int l, sem_handle h, const float *r, float 
     const double sigma = theta / delta;
     double rho_prev = 1.0 / sigma;
     if (zero) {
-        LAUNCH_V(cheb_fused_kernel, n, s, n, r, (const float *)nullptr, (const int32_t *)nullptr, L.perm, L.offs,
-                 L.Dinv32, d, x, 0.0f, (float)(1.0 / theta), 1);
+        LAUNCH_B(cheb_fused_kernel, n, vs, s, n, vs, n, r, (const float *)nullptr, L.Dinv32, d, x,
+                 0.0f, (float)(1.0 / theta), 1);
     } else {
-        SEM_TRY(apply_f32(L, x, t, h1, h2, s));
-        LAUNCH_V(cheb_fused_kernel, n, s, n, r, (const float *)t, (const int32_t *)nullptr, L.perm, L.offs,
-                 L.Dinv32, d, x, 0.0f, (float)(1.0 / theta), 0);
+        SEM_TRY(apply_f32(L, vs, x, t, h1, h2, s));
+        LAUNCH_B(cheb_fused_kernel, n, vs, s, n, vs, n, r, (const float *)t, L.Dinv32, d, x, 0.0f,
+                 (float)(1.0 / theta), 0);
     }
     for (int k = 1; k < deg; ++k) {
         const double rho = 1.0 / (2.0 * sigma - rho_prev);
-        SEM_TRY(apply_f32(L, x, t, h1, h2, s));
-        LAUNCH_V(cheb_fused_kernel, n, s, n, r, (const float *)t, (const int32_t *)nullptr, L.perm, L.offs,
-                 L.Dinv32, d, x, (float)(rho * rho_prev), (float)(2.0 * rho / delta), 0);
+        SEM_TRY(apply_f32(L, vs, x, t, h1, h2, s));
+        LAUNCH_B(cheb_fused_kernel, n, vs, s, n, vs, n, r, (const float *)t, L.Dinv32, d, x,
+                 (float)(rho * rho_prev), (float)(2.0 * rho / delta), 0);
         rho_prev = rho;
     }
     return SEM_OK;
@@ -677,152 +728,205 @@ struct SolveCfg {
     int maxit, check_every, deg, coarse_maxit;
 };
 
+// Vector arrays of one Krylov solve on a level: x may be the caller's array
+// (leading dimension ldx); r, p, w are workspace arrays [nv][L.nL].
+struct KrylovVecs {
+    double *x;
+    int64_t ldx;
+    double *r, *p, *w;
+    KrylovScalars *sc;
+};
+
 // enqueue Jacobi-PCG iterations first_iter .. first_iter+iters-1 (1-based)
-// on level L: operator with fused (p, A_L p), QQ^T, update with alpha, and
-// direction update with beta and the convergence decision -- four kernels per
-// iteration, no single-block reduction kernels
-static int pcg_iterations(const Level &L, const double *k, double h1, double h2, double *x,
-                          double *r, double *p, double *w, double *pax, double *partial,
-                          KrylovScalars *sc, int first_iter, int iters, hipStream_t s)
+// on level L for the batch vs: operator with fused (p, A_L p), QQ^T, update
+// with alpha, and direction update with beta and the convergence decision --
+// four kernels per iteration, no single-block reduction kernels
+static int pcg_iterations(sem_handle h, const Level &L, const VSet &vs, const double *k, double h1,
+                          double h2, const KrylovVecs &kv, int first_iter, int iters, hipStream_t s)
 {
+    Workspace &ws = h->ws;
     const int64_t n = L.nL;
     const int nbv = red_grid(n);
+    const int *skip = &kv.sc[0].done;
     for (int c = 0; c < iters; ++c) {
         const int it = first_iter + c;
         const int parity = (it - 1) & 1;
         int64_t nbax = 0;
-        SEM_TRY(launch_ax<double>(L, L.G, L.B, L.D, p, w, h1, h2, k, pax, &nbax, s, &sc->done));
-        SEM_TRY(launch_gs<double>(L, w, s, &sc->done));
-        LAUNCH_V(pcg_update_fused_kernel, n, s, n, sc, parity, (const double *)pax, nbax,
-                 (const double *)p, (const double *)w, (const int32_t *)nullptr, L.perm, L.offs,
-                 L.Dinv, L.W, x, r, partial);
-        LAUNCH_V(pcg_p_fused_kernel, n, s, n, sc, parity, it, (const double *)partial,
-                 (int64_t)nbv, L.Dinv, (const double *)r, p);
+        SEM_TRY(launch_ax_multi<double>(L, L.G, L.B, L.D, kv.p, n, kv.w, n, vs, h1, h2, k,
+                                        ws.partial_ax, ws.pst_ax, &nbax, s, skip, kScStride));
+        SEM_TRY(launch_gs_multi<double>(L, kv.w, n, vs, s, skip, kScStride));
+        LAUNCH_B(pcg_update_fused_kernel, n, vs, s, n, vs, n, kv.ldx, kv.sc, parity,
+                 (const double *)ws.partial_ax, ws.pst_ax, nbax, (const double *)kv.p,
+                 (const double *)kv.w, L.Dinv, L.W, kv.x, kv.r, ws.partial, ws.pst);
+        LAUNCH_B(pcg_p_fused_kernel, n, vs, s, n, vs, n, kv.sc, parity, it,
+                 (const double *)ws.partial, ws.pst, (int64_t)nbv, L.Dinv, (const double *)kv.r,
+                 kv.p);
     }
     return SEM_OK;
 }
 
-// start a Jacobi-PCG on level L: x given (Ax computed) or zero
-static int pcg_start(const Level &L, const double *k, double h1, double h2, const double *b,
-                     double *x, bool zero, double *r, double *p, double *w, double *partial,
-                     KrylovScalars *sc, double tol, int maxit, hipStream_t s)
+// start a Jacobi-PCG on level L for the batch vs: x given (Ax computed) or zero
+static int pcg_start(sem_handle h, const Level &L, const VSet &vs, const double *k, double h1,
+                     double h2, const double *b, int64_t ldb, const KrylovVecs &kv, bool zero,
+                     double tol, int maxit, hipStream_t s)
 {
+    Workspace &ws = h->ws;
     const int64_t n = L.nL;
     const double *Ax = nullptr;
     if (zero) {
-        LAUNCH_V(fill_kernel<double>, n, s, n, x, 0.0);
+        LAUNCH_B(fill_kernel<double>, n, vs, s, n, vs, kv.ldx, kv.x, 0.0);
     } else {
-        LAUNCH_V((mask_kernel<double, double>), n, s, n, L.W, x);
-        SEM_TRY(launch_ax<double>(L, L.G, L.B, L.D, x, w, h1, h2, k, nullptr, nullptr, s));
-        SEM_TRY(launch_gs<double>(L, w, s));
-        Ax = w;
+        LAUNCH_B((mask_kernel<double, double>), n, vs, s, n, vs, kv.ldx, L.W, kv.x);
+        SEM_TRY(launch_ax_multi<double>(L, L.G, L.B, L.D, kv.x, kv.ldx, kv.w, n, vs, h1, h2, k,
+                                        nullptr, 0, nullptr, s, nullptr, 0));
+        SEM_TRY(launch_gs_multi<double>(L, kv.w, n, vs, s, nullptr, 0));
+        Ax = kv.w;
     }
-    LAUNCH_V(pcg_init_kernel, n, s, n, b, Ax, L.Dinv, L.W, r, p, partial, 1);
-    LAUNCH_1(fin_init_kernel, s, partial, (int64_t)red_grid(n), sc, tol, maxit);
+    LAUNCH_B(pcg_init_kernel, n, vs, s, n, vs, ldb, b, n, Ax, L.Dinv, L.W, kv.r, kv.p, ws.partial,
+             ws.pst, 1);
+    LAUNCH_1B(fin_init_kernel, vs, s, vs, (const double *)ws.partial, ws.pst, (int64_t)red_grid(n),
+              kv.sc, tol, maxit);
     return SEM_OK;
 }
 
-// one V-cycle from level l: input rhs in mg_r[l] (FP32; FP64 on the coarsest),
-// output in mg_x[l]
-static int vcycle(sem_handle h, int l, const SolveCfg &cfg, hipStream_t s)
+// one V-cycle from level l for the batch vs: right-hand sides in mg_r[l]
+// (FP32; FP64 on the coarsest), output in mg_x[l], arrays [nv][nL of level l]
+static int vcycle(sem_handle h, int l, const VSet &vs, const SolveCfg &cfg, hipStream_t s)
 {
     Workspace &w = h->ws;
     const int lc = h->n_levels - 1;
     const Level &L = h->lv[l];
+    const int64_t n = L.nL;
     if (l == lc) {
-        double *b = (double *)w.mg_r[l], *x = (double *)w.mg_x[l];
-        SEM_TRY(pcg_start(L, nullptr, cfg.h1, cfg.h2, b, x, true, w.c_r, w.c_p, w.c_w, w.partial,
-                          w.sc_c, cfg.coarse_tol, cfg.coarse_maxit, s));
-        SEM_TRY(pcg_iterations(L, nullptr, cfg.h1, cfg.h2, x, w.c_r, w.c_p, w.c_w, w.partial_ax,
-                               w.partial, w.sc_c, 1, cfg.coarse_maxit, s));
+        double *b = (double *)w.mg_r[l];
+        const KrylovVecs kv{(double *)w.mg_x[l], n, w.c_r, w.c_p, w.c_w, w.sc_c};
+        SEM_TRY(pcg_start(h, L, vs, nullptr, cfg.h1, cfg.h2, b, n, kv, true, cfg.coarse_tol,
+                          cfg.coarse_maxit, s));
+        SEM_TRY(pcg_iterations(h, L, vs, nullptr, cfg.h1, cfg.h2, kv, 1, cfg.coarse_maxit, s));
         return SEM_OK;
     }
-    const int64_t n = L.nL;
     float *r = (float *)w.mg_r[l], *x = (float *)w.mg_x[l], *t = (float *)w.mg_t[l],
           *sres = (float *)w.mg_s[l];
     const double lmax = L.lmax;
     const double lmin_f = h->key.lo, lmax_f = h->key.hi;
     // pre-smoothing from x = 0
-    SEM_TRY(chebyshev(L, l, h, r, x, true, lmin_f * lmax, lmax_f * lmax, cfg.deg, cfg.h1, cfg.h2, s));
+    SEM_TRY(chebyshev(L, l, h, vs, r, x, true, lmin_f * lmax, lmax_f * lmax, cfg.deg, cfg.h1,
+                      cfg.h2, s));
     // restricted residual s = W (r - A x)
-    SEM_TRY(apply_f32(L, x, t, cfg.h1, cfg.h2, s));
-    LAUNCH_V(wresid_fused_kernel, n, s, n, L.W32, (const float *)r, (const float *)t,
-             (const int32_t *)nullptr, L.perm, L.offs, sres);
+    SEM_TRY(apply_f32(L, vs, x, t, cfg.h1, cfg.h2, s));
+    LAUNCH_B(wresid_fused_kernel, n, vs, s, n, vs, n, L.W32, (const float *)r, (const float *)t,
+             sres);
     const Level &C = h->lv[l + 1];
     const int64_t nc = C.nL;
     if (l + 1 == lc) {
-        // restrict in FP32 into t's coarse-sized head, then FP64 for the coarse solve
-        float *tc = t;  // n >= nc
-        SEM_TRY(launch_interp<float>(L.E, L.nq, C.nq, L.Jc32, sres, tc, true, s));
-        LAUNCH_V((convert_kernel<float, double>), nc, s, nc, tc, (double *)w.mg_r[l + 1]);
-        SEM_TRY(launch_gs<double>(C, (double *)w.mg_r[l + 1], s));
-        LAUNCH_V((mask_kernel<double, double>), nc, s, nc, C.W, (double *)w.mg_r[l + 1]);
-        SEM_TRY(vcycle(h, l + 1, cfg, s));
-        LAUNCH_V((convert_kernel<double, float>), nc, s, nc, (const double *)w.mg_x[l + 1], tc);
+        // restrict in FP32 into the head of t (n >= nc), then FP64 for the coarse solve
+        double *bc = (double *)w.mg_r[l + 1];
+        for (int q = 0; q < vs.n; ++q) {
+            const int64_t v = vs.at(q);
+            SEM_TRY(launch_interp<float>(L.E, L.nq, C.nq, L.Jc32, sres + v * n, t + v * n, true, s));
+        }
+        LAUNCH_B((convert_kernel<float, double>), nc, vs, s, nc, vs, n, (const float *)t, nc, bc);
+        SEM_TRY(launch_gs_multi<double>(C, bc, nc, vs, s, nullptr, 0));
+        LAUNCH_B((mask_kernel<double, double>), nc, vs, s, nc, vs, nc, C.W, bc);
+        SEM_TRY(vcycle(h, l + 1, vs, cfg, s));
+        LAUNCH_B((convert_kernel<double, float>), nc, vs, s, nc, vs, nc,
+                 (const double *)w.mg_x[l + 1], n, t);
         // prolong: x += J e_c  (sres reused for the fine-sized interpolant)
-        SEM_TRY(launch_interp<float>(L.E, C.nq, L.nq, L.Jc32, tc, sres, false, s));
+        for (int q = 0; q < vs.n; ++q) {
+            const int64_t v = vs.at(q);
+            SEM_TRY(launch_interp<float>(L.E, C.nq, L.nq, L.Jc32, t + v * n, sres + v * n, false, s));
+        }
     } else {
         float *rc = (float *)w.mg_r[l + 1];
-        SEM_TRY(launch_interp<float>(L.E, L.nq, C.nq, L.Jc32, sres, rc, true, s));
-        SEM_TRY(launch_gs<float>(C, rc, s));
-        LAUNCH_V((mask_kernel<float, float>), nc, s, nc, C.W32, rc);
-        SEM_TRY(vcycle(h, l + 1, cfg, s));
-        SEM_TRY(launch_interp<float>(L.E, C.nq, L.nq, L.Jc32, (const float *)w.mg_x[l + 1], sres,
-                                     false, s));
+        for (int q = 0; q < vs.n; ++q) {
+            const int64_t v = vs.at(q);
+            SEM_TRY(launch_interp<float>(L.E, L.nq, C.nq, L.Jc32, sres + v * n, rc + v * nc, true, s));
+        }
+        SEM_TRY(launch_gs_multi<float>(C, rc, nc, vs, s, nullptr, 0));
+        LAUNCH_B((mask_kernel<float, float>), nc, vs, s, nc, vs, nc, C.W32, rc);
+        SEM_TRY(vcycle(h, l + 1, vs, cfg, s));
+        const float *xc = (const float *)w.mg_x[l + 1];
+        for (int q = 0; q < vs.n; ++q) {
+            const int64_t v = vs.at(q);
+            SEM_TRY(launch_interp<float>(L.E, C.nq, L.nq, L.Jc32, xc + v * nc, sres + v * n, false, s));
+        }
     }
-    LAUNCH_V(add_kernel<float>, n, s, n, (const float *)sres, x);
+    LAUNCH_B(add_kernel<float>, n, vs, s, n, vs, n, (const float *)sres, x);
     // post-smoothing
-    SEM_TRY(chebyshev(L, l, h, r, x, false, lmin_f * lmax, lmax_f * lmax, cfg.deg, cfg.h1, cfg.h2, s));
+    SEM_TRY(chebyshev(L, l, h, vs, r, x, false, lmin_f * lmax, lmax_f * lmax, cfg.deg, cfg.h1,
+                      cfg.h2, s));
     return SEM_OK;
 }
 
-// z = M(r): V-cycle on the FP64 fine residual
-static int precondition_pmg(sem_handle h, const double *r, double *z, const SolveCfg &cfg,
-                            hipStream_t s)
+// z = M(r) for the batch vs: V-cycle on the FP64 fine residuals
+static int precondition_pmg(sem_handle h, const VSet &vs, const double *r, double *z,
+                            const SolveCfg &cfg, hipStream_t s)
 {
     Workspace &w = h->ws;
     const Level &F = h->lv[0];
     const int64_t n = F.nL;
-    LAUNCH_V((convert_kernel<double, float>), n, s, n, r, (float *)w.mg_r[0]);
-    SEM_TRY(vcycle(h, 0, cfg, s));
-    LAUNCH_V((convert_kernel<float, double>), n, s, n, (const float *)w.mg_x[0], z);
-    LAUNCH_V((mask_kernel<double, double>), n, s, n, F.W, z);
+    LAUNCH_B((convert_kernel<double, float>), n, vs, s, n, vs, n, r, n, (float *)w.mg_r[0]);
+    SEM_TRY(vcycle(h, 0, vs, cfg, s));
+    LAUNCH_B((convert_kernel<float, double>), n, vs, s, n, vs, n, (const float *)w.mg_x[0], n, z);
+    LAUNCH_B((mask_kernel<double, double>), n, vs, s, n, vs, n, F.W, z);
     return SEM_OK;
 }
 
-static int read_scalars(sem_handle h, const KrylovScalars *sc, KrylovScalars *out, hipStream_t s)
+// host copies of the outer (and coarse) scalars of every vector slot
+static int read_scalars(sem_handle h, bool coarse, hipStream_t s)
 {
-    SEM_HIP(hipMemcpyAsync(h->ws.host_sc, sc, sizeof(KrylovScalars), hipMemcpyDeviceToHost, s));
+    Workspace &w = h->ws;
+    SEM_HIP(hipMemcpyAsync(w.host_sc, w.sc, kMaxRhs * sizeof(KrylovScalars), hipMemcpyDeviceToHost, s));
+    if (coarse)
+        SEM_HIP(hipMemcpyAsync(w.host_sc + kMaxRhs, w.sc_c, kMaxRhs * sizeof(KrylovScalars),
+                               hipMemcpyDeviceToHost, s));
     SEM_HIP(hipStreamSynchronize(s));
-    *out = *h->ws.host_sc;
     return SEM_OK;
 }
 
-// true residual ||b - A x||_W / ||b||_W in FP64
-static int true_residual(sem_handle h, const double *k, double h1, double h2, const double *b,
-                         const double *x, double *rel, hipStream_t s)
+// vectors of `all` whose solve is still running
+static VSet live_set(const Workspace &w, const VSet &all)
+{
+    VSet act{0, 0u};
+    for (int q = 0; q < all.n; ++q)
+        if (!w.host_sc[all.at(q)].done) act.push(all.at(q));
+    return act;
+}
+
+// true residuals ||b - A x||_W / ||b||_W in FP64 for the batch vs
+static int true_residual(sem_handle h, const VSet &vs, const double *k, double h1, double h2,
+                         const double *b, const double *x, int64_t ld, double *rel, hipStream_t s)
 {
     const Level &F = h->lv[0];
     Workspace &w = h->ws;
-    SEM_TRY(launch_ax<double>(F, F.G, F.B, F.D, x, w.w, h1, h2, k, nullptr, nullptr, s));
-    SEM_TRY(launch_gs<double>(F, w.w, s));
+    const int64_t n = F.nL;
+    SEM_TRY(launch_ax_multi<double>(F, F.G, F.B, F.D, x, ld, w.w, n, vs, h1, h2, k, nullptr, 0,
+                                    nullptr, s, nullptr, 0));
+    SEM_TRY(launch_gs_multi<double>(F, w.w, n, vs, s, nullptr, 0));
     // pcg_init computes (W r r, W b b) for r = b - Ax
-    LAUNCH_V(pcg_init_kernel, F.nL, s, F.nL, b, (const double *)w.w, F.Dinv, F.W, w.z,
-             (double *)nullptr, w.partial, 0);
-    const int nb = red_grid(F.nL);
-    std::vector<double> hp(3 * nb);
-    SEM_HIP(hipMemcpyAsync(hp.data(), w.partial, sizeof(double) * 3 * nb, hipMemcpyDeviceToHost, s));
+    LAUNCH_B(pcg_init_kernel, n, vs, s, n, vs, ld, b, n, (const double *)w.w, F.Dinv, F.W, w.z,
+             (double *)nullptr, w.partial, w.pst, 0);
+    const int nb = red_grid(n);
+    std::vector<double> hp((size_t)3 * nb * vs.n);
+    for (int q = 0; q < vs.n; ++q)
+        SEM_HIP(hipMemcpyAsync(hp.data() + (size_t)3 * nb * q, w.partial + vs.at(q) * w.pst,
+                               sizeof(double) * 3 * nb, hipMemcpyDeviceToHost, s));
     SEM_HIP(hipStreamSynchronize(s));
-    double rr = 0, bb = 0;
-    for (int i = 0; i < nb; ++i) {
-        rr += hp[3 * i + 1];
-        bb += hp[3 * i + 2];
+    for (int q = 0; q < vs.n; ++q) {
+        double rr = 0, bb = 0;
+        const double *pq = hp.data() + (size_t)3 * nb * q;
+        for (int i = 0; i < nb; ++i) {
+            rr += pq[3 * i + 1];
+            bb += pq[3 * i + 2];
+        }
+        rel[q] = bb > 0 ? std::sqrt(rr / bb) : 0.0;
     }
-    *rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
     return SEM_OK;
 }
 
-int pcg_solve(sem_handle h, const double *b, double *x, const sem_solve_opts *o,
+// nv solves with one operator, in lockstep: vector v's right-hand side and
+// iterate are b + v*ld and x + v*ld; every kernel serves the unconverged ones
+int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, const sem_solve_opts *o,
               sem_solve_stats *st, hipStream_t s)
 {
     using clk = std::chrono::steady_clock;
@@ -838,7 +942,7 @@ int pcg_solve(sem_handle h, const double *b, double *x, const sem_solve_opts *o,
     SolveCfg cfg{o->h1, o->h2, o->tol, o->coarse_tol, o->maxit, std::max(1, o->check_every),
                  std::max(1, o->cheb_degree), std::max(1, o->coarse_maxit)};
     const auto t0 = clk::now();
-    SEM_TRY(ensure_workspace(h, pmg));
+    SEM_TRY(ensure_workspace(h, pmg, nv));
     Workspace &w = h->ws;
     const Level &F = h->lv[0];
     const int64_t n = F.nL;
@@ -873,87 +977,106 @@ int pcg_solve(sem_handle h, const double *b, double *x, const sem_solve_opts *o,
     SEM_HIP(hipStreamSynchronize(s));
     const auto t1 = clk::now();
 
-    KrylovScalars hs{};
-    int coarse_total = 0;
+    const VSet all = VSet::first(nv);
+    const KrylovVecs kv{x, ld, w.r, w.p, w.w, w.sc};
+    std::vector<int> coarse_total(nv, 0);
     if (!pmg) {
-        SEM_TRY(pcg_start(F, o->k, o->h1, o->h2, b, x, o->zero_guess != 0, w.r, w.p, w.w, w.partial,
-                          w.sc, o->tol, o->maxit, s));
-        SEM_TRY(read_scalars(h, w.sc, &hs, s));
+        SEM_TRY(pcg_start(h, F, all, o->k, o->h1, o->h2, b, ld, kv, o->zero_guess != 0, o->tol,
+                          o->maxit, s));
+        SEM_TRY(read_scalars(h, false, s));
+        VSet act = live_set(w, all);
         int it = 0;
-        while (!hs.done) {
-            SEM_TRY(pcg_iterations(F, o->k, o->h1, o->h2, x, w.r, w.p, w.w, w.partial_ax, w.partial,
-                                   w.sc, it + 1, cfg.check_every, s));
+        while (act.n > 0) {
+            SEM_TRY(pcg_iterations(h, F, act, o->k, o->h1, o->h2, kv, it + 1, cfg.check_every, s));
             it += cfg.check_every;
-            SEM_TRY(read_scalars(h, w.sc, &hs, s));
+            SEM_TRY(read_scalars(h, false, s));
+            act = live_set(w, act);
         }
     } else {
         // r = b - A x ; z = M r ; p = z ; rz = (z, r)
         const double *Ax = nullptr;
         if (o->zero_guess) {
-            LAUNCH_V(fill_kernel<double>, n, s, n, x, 0.0);
+            LAUNCH_B(fill_kernel<double>, n, all, s, n, all, ld, x, 0.0);
         } else {
-            LAUNCH_V((mask_kernel<double, double>), n, s, n, F.W, x);
-            SEM_TRY(launch_ax<double>(F, F.G, F.B, F.D, x, w.w, o->h1, o->h2, nullptr, nullptr, nullptr, s));
-            SEM_TRY(launch_gs<double>(F, w.w, s));
+            LAUNCH_B((mask_kernel<double, double>), n, all, s, n, all, ld, F.W, x);
+            SEM_TRY(launch_ax_multi<double>(F, F.G, F.B, F.D, x, ld, w.w, n, all, o->h1, o->h2,
+                                            nullptr, nullptr, 0, nullptr, s, nullptr, 0));
+            SEM_TRY(launch_gs_multi<double>(F, w.w, n, all, s, nullptr, 0));
             Ax = w.w;
         }
-        LAUNCH_V(pcg_init_kernel, n, s, n, b, Ax, F.Dinv, F.W, w.r, (double *)nullptr, w.partial, 0);
-        LAUNCH_1(fin_init_kernel, s, w.partial, (int64_t)red_grid(n), w.sc, o->tol, o->maxit);
-        SEM_TRY(read_scalars(h, w.sc, &hs, s));
+        LAUNCH_B(pcg_init_kernel, n, all, s, n, all, ld, b, n, Ax, F.Dinv, F.W, w.r,
+                 (double *)nullptr, w.partial, w.pst, 0);
+        LAUNCH_1B(fin_init_kernel, all, s, all, (const double *)w.partial, w.pst,
+                  (int64_t)red_grid(n), w.sc, o->tol, o->maxit);
+        SEM_TRY(read_scalars(h, false, s));
+        VSet act = live_set(w, all);
         const int nbv = red_grid(n);
-        if (!hs.done) {
-            SEM_TRY(precondition_pmg(h, w.r, w.z, cfg, s));
-            LAUNCH_V(dot_zw_kernel, n, s, n, (const KrylovScalars *)w.sc, F.W, (const double *)w.z,
-                     (const double *)w.r, (const double *)w.r, w.partial);
-            LAUNCH_V(fcg_p_fused_kernel, n, s, n, w.sc, 1, (const double *)w.partial, (int64_t)nbv,
-                     (const double *)w.z, w.p, 1);
+        const int *skip = &w.sc[0].done;
+        VSet cycled{0, 0u};  // vectors whose coarse counts are still to be read
+        if (act.n > 0) {
+            SEM_TRY(precondition_pmg(h, act, w.r, w.z, cfg, s));
+            LAUNCH_B(dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
+                     (const double *)w.z, (const double *)w.r, (const double *)w.r, w.partial, w.pst);
+            LAUNCH_B(fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, 1, (const double *)w.partial,
+                     w.pst, (int64_t)nbv, (const double *)w.z, w.p, 1);
+            cycled = act;
         }
-        for (int it = 0; !hs.done; ++it) {
+        for (int it = 0; act.n > 0; ++it) {
             const int parity = it & 1;
             int64_t nbax = 0;
-            SEM_TRY(launch_ax<double>(F, F.G, F.B, F.D, w.p, w.w, o->h1, o->h2, nullptr, w.partial_ax,
-                                      &nbax, s, &w.sc->done));
-            SEM_TRY(launch_gs<double>(F, w.w, s, &w.sc->done));
-            LAUNCH_V(fcg_update_fused_kernel, n, s, n, w.sc, parity, (const double *)w.partial_ax,
-                     nbax, (const double *)w.p, (const double *)w.w, (const int32_t *)nullptr, F.perm,
-                     F.offs, F.W, x, w.r, w.partial);
-            LAUNCH_1(fin_conv_kernel, s, w.partial, (int64_t)nbv, w.sc);
-            SEM_TRY(read_scalars(h, w.sc, &hs, s));
-            if (hs.done) break;
-            SEM_TRY(precondition_pmg(h, w.r, w.z, cfg, s));
-            LAUNCH_V(dot_zw_kernel, n, s, n, (const KrylovScalars *)w.sc, F.W, (const double *)w.z,
-                     (const double *)w.w, (const double *)w.r, w.partial);
-            LAUNCH_V(fcg_p_fused_kernel, n, s, n, w.sc, parity, (const double *)w.partial,
-                     (int64_t)nbv, (const double *)w.z, w.p, 0);
-            KrylovScalars csc{};
-            SEM_HIP(hipMemcpyAsync(&w.host_sc[1], w.sc_c, sizeof(KrylovScalars), hipMemcpyDeviceToHost, s));
-            SEM_TRY(read_scalars(h, w.sc, &hs, s));
-            csc = w.host_sc[1];
-            coarse_total += csc.iters;
+            SEM_TRY(launch_ax_multi<double>(F, F.G, F.B, F.D, w.p, n, w.w, n, act, o->h1, o->h2,
+                                            nullptr, w.partial_ax, w.pst_ax, &nbax, s, skip,
+                                            kScStride));
+            SEM_TRY(launch_gs_multi<double>(F, w.w, n, act, s, skip, kScStride));
+            LAUNCH_B(fcg_update_fused_kernel, n, act, s, n, act, n, ld, w.sc, parity,
+                     (const double *)w.partial_ax, w.pst_ax, nbax, (const double *)w.p,
+                     (const double *)w.w, F.W, x, w.r, w.partial, w.pst);
+            LAUNCH_1B(fin_conv_kernel, act, s, act, (const double *)w.partial, w.pst, (int64_t)nbv,
+                      w.sc);
+            // one host synchronisation per iteration: outer scalars, and the
+            // coarse-solve counts of the V-cycle that preceded this update
+            SEM_TRY(read_scalars(h, cycled.n > 0, s));
+            for (int q = 0; q < cycled.n; ++q)
+                coarse_total[cycled.at(q)] += w.host_sc[kMaxRhs + cycled.at(q)].iters;
+            cycled = VSet{0, 0u};
+            act = live_set(w, act);
+            if (act.n == 0) break;
+            SEM_TRY(precondition_pmg(h, act, w.r, w.z, cfg, s));
+            LAUNCH_B(dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
+                     (const double *)w.z, (const double *)w.w, (const double *)w.r, w.partial, w.pst);
+            LAUNCH_B(fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, parity,
+                     (const double *)w.partial, w.pst, (int64_t)nbv, (const double *)w.z, w.p, 0);
+            cycled = act;
         }
     }
     const auto t2 = clk::now();
-    double trr = 0.0;
-    SEM_TRY(true_residual(h, o->k, o->h1, o->h2, b, x, &trr, s));
-    if (st) {
-        st->iters = hs.iters;
-        st->rel_res = hs.bb > 0 ? std::sqrt(std::max(hs.rr, 0.0) / hs.bb) : 0.0;
-        st->converged = (hs.status == SEM_OK && (hs.bb == 0.0 || hs.rr <= hs.tol2)) ? 1 : 0;
-        st->true_rel_res = trr;
-        st->ms_setup = std::chrono::duration<double, std::milli>(t1 - t0).count();
-        st->ms_solve = std::chrono::duration<double, std::milli>(t2 - t1).count();
-        st->coarse_iters = coarse_total;
+    std::vector<KrylovScalars> hs(w.host_sc, w.host_sc + nv);
+    std::vector<double> trr(nv, 0.0);
+    SEM_TRY(true_residual(h, all, o->k, o->h1, o->h2, b, x, ld, trr.data(), s));
+    int rc = SEM_OK;
+    for (int v = 0; v < nv; ++v) {
+        const KrylovScalars &q = hs[v];
+        const bool conv = q.status == SEM_OK && (q.bb == 0.0 || q.rr <= q.tol2);
+        if (st) {
+            st[v].iters = q.iters;
+            st[v].rel_res = q.bb > 0 ? std::sqrt(std::max(q.rr, 0.0) / q.bb) : 0.0;
+            st[v].converged = conv ? 1 : 0;
+            st[v].true_rel_res = trr[v];
+            st[v].ms_setup = std::chrono::duration<double, std::milli>(t1 - t0).count();
+            st[v].ms_solve = std::chrono::duration<double, std::milli>(t2 - t1).count();
+            st[v].coarse_iters = coarse_total[v];
+        }
+        if (q.status == SEM_EBREAKDOWN) {
+            if (rc != SEM_EBREAKDOWN)
+                set_error("sem_pcg_solve: breakdown of system %d after %d iterations", v, q.iters);
+            rc = SEM_EBREAKDOWN;
+        } else if (!conv && rc == SEM_OK) {
+            set_error("sem_pcg_solve: system %d not converged after %d iterations (rel res %.3e)", v,
+                      q.iters, q.bb > 0 ? std::sqrt(q.rr / q.bb) : 0.0);
+            rc = SEM_ENOCONV;
+        }
     }
-    if (hs.status == SEM_EBREAKDOWN) {
-        set_error("sem_pcg_solve: breakdown after %d iterations", hs.iters);
-        return SEM_EBREAKDOWN;
-    }
-    if (!(hs.bb == 0.0 || hs.rr <= hs.tol2)) {
-        set_error("sem_pcg_solve: not converged after %d iterations (rel res %.3e)", hs.iters,
-                  hs.bb > 0 ? std::sqrt(hs.rr / hs.bb) : 0.0);
-        return SEM_ENOCONV;
-    }
-    return SEM_OK;
+    return rc;
 }
 
 // b = R QQ^T (B o f)
@@ -961,9 +1084,10 @@ int assemble_load(sem_handle h, const double *f, double *b, hipStream_t s)
 {
     const Level &F = h->lv[0];
     const int64_t n = F.nL;
+    const VSet one = VSet::one();
     LAUNCH_V(mass_kernel, n, s, n, F.B, f, b);
     SEM_TRY(launch_gs<double>(F, b, s));
-    LAUNCH_V((mask_kernel<double, double>), n, s, n, F.W, b);
+    LAUNCH_B((mask_kernel<double, double>), n, one, s, n, one, (int64_t)0, F.W, b);
     return SEM_OK;
 }
 
@@ -972,17 +1096,18 @@ int adjoint(sem_handle h, const double *u, const double *g, const sem_solve_opts
 {
     const Level &F = h->lv[0];
     const int64_t n = F.nL;
-    SEM_TRY(ensure_workspace(h, false));
+    SEM_TRY(ensure_workspace(h, false, 1));
     if (!h->ws.aux) SEM_HIP(hipMalloc(&h->ws.aux, sizeof(double) * n));
     // right-hand side R QQ^T g in a workspace vector the solver does not touch
     double *rhs = h->ws.aux;
     SEM_HIP(hipMemcpyAsync(rhs, g, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     SEM_TRY(launch_gs<double>(F, rhs, s));
-    LAUNCH_V((mask_kernel<double, double>), n, s, n, F.W, rhs);
+    const VSet one = VSet::one();
+    LAUNCH_B((mask_kernel<double, double>), n, one, s, n, one, (int64_t)0, F.W, rhs);
     sem_solve_opts oo = *o;
     oo.zero_guess = 1;
     if (oo.k != nullptr || h->n_levels < 2) oo.precond = SEM_PRECOND_JACOBI;
-    const int rc = pcg_solve(h, rhs, lam, &oo, st, s);
+    const int rc = pcg_solve(h, 1, rhs, lam, n, &oo, st, s);
     if (rc != SEM_OK && rc != SEM_ENOCONV) return rc;
     if (grad_f) LAUNCH_V(mass_kernel, n, s, n, F.B, lam, grad_f);
     if (grad_k) SEM_TRY(launch_grad_k(F, u, lam, o->h1, grad_k, s));
@@ -1034,6 +1159,20 @@ void sem_solve_opts_default(sem_solve_opts *o)
     o->zero_guess = 1;
 }
 
+static int check_solve_opts(const char *who, const sem_solve_opts *o)
+{
+    if (!(o->tol >= 0.0) || o->maxit < 0 || (o->precond != SEM_PRECOND_JACOBI && o->precond != SEM_PRECOND_PMG)) {
+        set_error("%s: bad options", who);
+        return SEM_EINVAL;
+    }
+    if (o->precond == SEM_PRECOND_PMG &&
+        (!(o->cheb_hi > o->cheb_lo) || !(o->cheb_lo > 0.0) || o->lanczos_steps < 2)) {
+        set_error("%s: bad Chebyshev options", who);
+        return SEM_EINVAL;
+    }
+    return SEM_OK;
+}
+
 int sem_pcg_solve(sem_handle h, const double *b, double *x, const sem_solve_opts *o,
                   sem_solve_stats *st, void *stream)
 {
@@ -1041,16 +1180,28 @@ int sem_pcg_solve(sem_handle h, const double *b, double *x, const sem_solve_opts
         set_error("sem_pcg_solve: null argument");
         return SEM_EINVAL;
     }
-    if (!(o->tol >= 0.0) || o->maxit < 0 || (o->precond != SEM_PRECOND_JACOBI && o->precond != SEM_PRECOND_PMG)) {
-        set_error("sem_pcg_solve: bad options");
+    SEM_TRY(check_solve_opts("sem_pcg_solve", o));
+    return pcg_solve(h, 1, b, x, h->lv[0].nL, o, st, (hipStream_t)stream);
+}
+
+int sem_pcg_solve_multi(sem_handle h, int nrhs, const double *b, double *x, int64_t ld,
+                        const sem_solve_opts *o, sem_solve_stats *st, void *stream)
+{
+    if (!h || !b || !x || !o) {
+        set_error("sem_pcg_solve_multi: null argument");
         return SEM_EINVAL;
     }
-    if (o->precond == SEM_PRECOND_PMG &&
-        (!(o->cheb_hi > o->cheb_lo) || !(o->cheb_lo > 0.0) || o->lanczos_steps < 2)) {
-        set_error("sem_pcg_solve: bad Chebyshev options");
+    if (nrhs < 1 || nrhs > kMaxRhs) {
+        set_error("sem_pcg_solve_multi: nrhs = %d outside 1..%d", nrhs, kMaxRhs);
         return SEM_EINVAL;
     }
-    return pcg_solve(h, b, x, o, st, (hipStream_t)stream);
+    if (ld < h->lv[0].nL) {
+        set_error("sem_pcg_solve_multi: ld = %lld below n_local = %lld", (long long)ld,
+                  (long long)h->lv[0].nL);
+        return SEM_EINVAL;
+    }
+    SEM_TRY(check_solve_opts("sem_pcg_solve_multi", o));
+    return pcg_solve(h, nrhs, b, x, ld, o, st, (hipStream_t)stream);
 }
 
 }  // extern "C"

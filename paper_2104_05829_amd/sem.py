@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libsem.so")
 SEM_OK, SEM_EINVAL, SEM_ENOMEM, SEM_EHIP, SEM_ENOCONV, SEM_EBREAKDOWN, SEM_EMESH = 0, -1, -2, -3, -4, -5, -6
 SEM_F64, SEM_F32 = 0, 1
 SEM_PRECOND_JACOBI, SEM_PRECOND_PMG = 0, 1
+SEM_MAX_RHS = 4
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 
@@ -79,6 +80,15 @@ _SIGS = {
     "sem_ax_level": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, _VP, ctypes.c_double,
                                     ctypes.c_double, _VP]),
     "sem_gs_level": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, _VP]),
+    "sem_ax_multi": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, ctypes.c_int64, ctypes.c_double,
+                                    ctypes.c_double, _VP]),
+    "sem_gs_multi": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int64, _VP]),
+    "sem_ax_level_multi": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP,
+                                          ctypes.c_int64, ctypes.c_double, ctypes.c_double, _VP]),
+    "sem_gs_level_multi": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP,
+                                          ctypes.c_int64, _VP]),
+    "sem_pcg_solve_multi": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, ctypes.c_int64,
+                                           ctypes.POINTER(SemSolveOpts), _VP, _VP]),
     "sem_solve_opts_default": (None, [ctypes.POINTER(SemSolveOpts)]),
     "sem_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(SemSolveOpts),
                                      ctypes.POINTER(SemSolveStats), _VP]),
@@ -158,6 +168,21 @@ def _dev_ptr(t, dtype, n, name):
     if n is not None and t.numel() != n:
         raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_batch(t, dtype, n, name):
+    """(pointer, nrhs, ld) of a [nrhs, n] device tensor with unit inner stride."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() != 2 or t.shape[1] != n or t.stride(1) != 1 or (t.shape[0] > 1 and t.stride(0) < n):
+        raise ValueError(f"{name} must be [nrhs, {n}] with rows of unit stride, got shape "
+                         f"{tuple(t.shape)} strides {t.stride()}")
+    return ctypes.c_void_p(t.data_ptr()), int(t.shape[0]), int(t.stride(0))
 
 
 class Sem:
@@ -254,6 +279,48 @@ class Sem:
         _check(lib().sem_gs_level(self._handle(), level, dt, pv, _stream()), "sem_gs_level")
         return v
 
+    def ax_multi(self, U, W=None, h1=1.0, h2=0.0):
+        """Operator on the rows of U ([nrhs, n_local] FP64); G read once per batch."""
+        torch = _torch()
+        if W is None:
+            W = torch.empty_like(U)
+        pu, nr, ld = _dev_batch(U, torch.float64, self.n_local, "U")
+        pw, nrw, ldw = _dev_batch(W, torch.float64, self.n_local, "W")
+        if nrw != nr or ldw != ld:
+            raise ValueError("U and W must have the same shape and strides")
+        _check(lib().sem_ax_multi(self._handle(), nr, pu, pw, ld, float(h1), float(h2), _stream()),
+               "sem_ax_multi")
+        return W
+
+    def gs_multi(self, V):
+        torch = _torch()
+        pv, nr, ld = _dev_batch(V, torch.float64, self.n_local, "V")
+        _check(lib().sem_gs_multi(self._handle(), nr, pv, ld, _stream()), "sem_gs_multi")
+        return V
+
+    def ax_level_multi(self, level, U, W=None, h1=1.0, h2=0.0):
+        torch = _torch()
+        if W is None:
+            W = torch.empty_like(U)
+        dt = SEM_F64 if U.dtype == torch.float64 else SEM_F32
+        n = self.info(level)["n_local"]
+        pu, nr, ld = _dev_batch(U, U.dtype, n, "U")
+        pw, nrw, ldw = _dev_batch(W, U.dtype, n, "W")
+        if nrw != nr or ldw != ld:
+            raise ValueError("U and W must have the same shape and strides")
+        _check(lib().sem_ax_level_multi(self._handle(), level, dt, nr, pu, pw, ld, float(h1), float(h2),
+                                        _stream()), "sem_ax_level_multi")
+        return W
+
+    def gs_level_multi(self, level, V):
+        torch = _torch()
+        dt = SEM_F64 if V.dtype == torch.float64 else SEM_F32
+        n = self.info(level)["n_local"]
+        pv, nr, ld = _dev_batch(V, V.dtype, n, "V")
+        _check(lib().sem_gs_level_multi(self._handle(), level, dt, nr, pv, ld, _stream()),
+               "sem_gs_level_multi")
+        return V
+
     def grad_k(self, u, lam, h1=1.0, out=None):
         torch = _torch()
         if out is None:
@@ -331,6 +398,25 @@ class Sem:
         if raise_on_error and rc not in (SEM_OK, SEM_ENOCONV):
             _check(rc, "sem_pcg_solve")
         return x, st.as_dict(), rc
+
+    def solve_multi(self, B, X=None, raise_on_error=True, **kw):
+        """nrhs solves with one operator in lockstep (rows of B, [nrhs, n_local],
+        nrhs <= SEM_MAX_RHS); returns (X, [stats dict per row], status)."""
+        torch = _torch()
+        o = self._opts(kw)
+        if X is None:
+            X = torch.zeros_like(B)
+            o.zero_guess = 1
+        pb, nr, ld = _dev_batch(B, torch.float64, self.n_local, "B")
+        px, nrx, ldx = _dev_batch(X, torch.float64, self.n_local, "X")
+        if nrx != nr or ldx != ld:
+            raise ValueError("B and X must have the same shape and strides")
+        st = (SemSolveStats * max(nr, 1))()
+        rc = lib().sem_pcg_solve_multi(self._handle(), nr, pb, px, ld, ctypes.byref(o),
+                                       ctypes.cast(st, _VP), _stream())
+        if raise_on_error and rc not in (SEM_OK, SEM_ENOCONV):
+            _check(rc, "sem_pcg_solve_multi")
+        return X, [st[i].as_dict() for i in range(nr)], rc
 
     # -- introspection ----------------------------------------------------
     def info(self, level=0):

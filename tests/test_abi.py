@@ -23,7 +23,8 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for required in ("sem_setup", "sem_ax", "sem_gs", "sem_pcg_solve", "sem_grad_k", "sem_free",
-                     "sem_rhs", "sem_adjoint", "sem_strerror", "sem_last_error"):
+                     "sem_rhs", "sem_adjoint", "sem_strerror", "sem_last_error", "sem_ax_multi",
+                     "sem_gs_multi", "sem_pcg_solve_multi"):
         assert required in names
     assert len(names) >= 16
 
@@ -105,6 +106,11 @@ def test_host_error_paths():
     assert L.sem_grad_k(None, None, None, 1.0, None, None) == S.SEM_EINVAL
     assert L.sem_ax_level(None, 0, 0, None, None, 1.0, 0.0, None) == S.SEM_EINVAL
     assert L.sem_gs_level(None, 0, 0, None, None) == S.SEM_EINVAL
+    assert L.sem_ax_multi(None, 3, None, None, 10, 1.0, 0.0, None) == S.SEM_EINVAL
+    assert L.sem_gs_multi(None, 3, None, 10, None) == S.SEM_EINVAL
+    assert L.sem_ax_level_multi(None, 0, 0, 3, None, None, 10, 1.0, 0.0, None) == S.SEM_EINVAL
+    assert L.sem_gs_level_multi(None, 0, 0, 3, None, 10, None) == S.SEM_EINVAL
+    assert L.sem_pcg_solve_multi(None, 3, None, None, 10, ctypes.byref(o), None, None) == S.SEM_EINVAL
     info = S.SemInfo()
     assert L.sem_info(None, 0, ctypes.byref(info)) == S.SEM_EINVAL
 
