@@ -22,7 +22,7 @@ void set_error(const char *fmt, ...)
 
 static void free_level(Level &L)
 {
-    void *ptrs[] = {L.G, L.B, L.G32, L.B32, L.W, L.W32, L.gid, L.dir, L.perm, L.offs, L.segid,
+    void *ptrs[] = {L.G, L.B, L.G32, L.B32, L.W, L.W32, L.gid, L.dir, L.perm, L.offs,
                     L.chunk_b, L.chunk_e, L.chunk_mask, L.over,
                     L.D, L.D32, L.Jc, L.Jc32, L.Dinv, L.Dinv32};
     for (void *p : ptrs)

@@ -4,7 +4,6 @@
 //   perm     local indices of copies of nodes with 2+ copies, sorted by
 //            (pointer, local index)  -- a stable radix sort of (g, l) pairs,
 //   offs     start of each such node's run in perm (plus the total at the end),
-//   segid    per copy, the run (segment) of its node in perm, -1 if unshared,
 //   W        counting weight 1/mult, 0 on Dirichlet copies (Sec. 3.4),
 // and check that all copies of a node agree in coordinates and Dirichlet flag.
 #include <hipcub/hipcub.hpp>
@@ -40,7 +39,6 @@ __global__ void run_fill_kernel(int64_t nruns, const int64_t *__restrict__ key,
                                 const int32_t *__restrict__ copyoff,
                                 const int32_t *__restrict__ sorted_idx,
                                 int32_t *__restrict__ perm, int32_t *__restrict__ offs,
-                                int32_t *__restrict__ segid,
                                 int32_t *__restrict__ mult, const double *__restrict__ x,
                                 const double *__restrict__ y, const double *__restrict__ z,
                                 const uint8_t *__restrict__ dir, double tol, int *bad)
@@ -49,24 +47,17 @@ __global__ void run_fill_kernel(int64_t nruns, const int64_t *__restrict__ key,
     if (r >= nruns) return;
     const int c = cnt[r], s0 = start[r];
     if (key[r] == 0) {
-        for (int t = 0; t < c; ++t) {
-            mult[sorted_idx[s0 + t]] = 1;
-            segid[sorted_idx[s0 + t]] = -1;
-        }
+        for (int t = 0; t < c; ++t) mult[sorted_idx[s0 + t]] = 1;
         return;
     }
     for (int t = 0; t < c; ++t) mult[sorted_idx[s0 + t]] = c;
-    if (c < 2) {
-        segid[sorted_idx[s0]] = -1;
-        return;
-    }
+    if (c < 2) return;
     const int so = segidx[r], co = copyoff[r];
     offs[so] = co;
     const int l0 = sorted_idx[s0];
     for (int t = 0; t < c; ++t) {
         const int l = sorted_idx[s0 + t];
         perm[co + t] = l;
-        segid[l] = so;
         if (x) {
             const double dx = fabs(x[l] - x[l0]), dy = fabs(y[l] - y[l0]), dz = fabs(z[l] - z[l0]);
             const double sc = 1.0 + fabs(x[l0]) + fabs(y[l0]) + fabs(z[l0]);
@@ -192,11 +183,10 @@ int build_maps(Level &L, const int64_t *gid, const uint8_t *dir, const double *x
     }
     SEM_HIP(hipMalloc(&L.perm, sizeof(int32_t) * (L.ncopies > 0 ? L.ncopies : 1)));
     SEM_HIP(hipMalloc(&L.offs, sizeof(int32_t) * (L.nseg + 1)));
-    SEM_HIP(hipMalloc(&L.segid, sizeof(int32_t) * nL));
     hipLaunchKernelGGL(run_fill_kernel, dim3(nbR), dim3(bs), 0, s, nruns, (const int64_t *)uniq.p,
                        (const int32_t *)cnt.p, (const int32_t *)start.p,
                        (const int32_t *)segidx.p, (const int32_t *)copyoff.p,
-                       (const int32_t *)vout.p, L.perm, L.offs, L.segid, (int32_t *)mult.p, x, y, z, dir,
+                       (const int32_t *)vout.p, L.perm, L.offs, (int32_t *)mult.p, x, y, z, dir,
                        1e-12, bad);
     SEM_HIP(hipGetLastError());
     const int32_t last = (int32_t)L.ncopies;

@@ -348,4 +348,213 @@ template int launch_interp<double>(int64_t, int, int, const double *, const doub
 template int launch_interp<float>(int64_t, int, int, const float *, const float *, float *, bool,
                                   hipStream_t);
 
+
+// ---------------------------------------------------------------------------
+// Fused p-multigrid transfers between a smoother level F (nq_F <= 8, so an
+// element's (i,j) columns fit one wavefront) and the next coarser level C, for
+// a batch of vectors (grid.y).  J = F.Jc32 [nq_F][nq_C] interpolates coarse
+// nodes to fine points (Sec. 3.4: the coarse spaces are nested, J the
+// tensor-product Lagrange interpolation).  A lane owns fine column (i,j) and
+// its k-line; contractions run k in registers, then j and i through LDS.
+//   restriction: out_C = mask_C o (J^T (x) J^T (x) J^T) [W_F (r - t)]
+//   prolongation: x_F += (J (x) J (x) J) in_C
+// Masking the restricted residual before QQ^T equals masking after it: all
+// copies of a Dirichlet node carry W = 0.
+// ---------------------------------------------------------------------------
+template <int NF>
+struct XferShape {
+    static constexpr int TPE = NF * NF;
+    static constexpr int EPB = 64 / TPE;
+    static constexpr int LDI = (NF % 2 == 0) ? NF + 1 : NF;
+};
+
+template <int NF, typename TO>
+__global__ void __launch_bounds__(64)
+restrict_resid_kernel(int64_t E, int nc, const float *__restrict__ J, const float *__restrict__ W,
+                      const float *__restrict__ r, const float *__restrict__ t, int64_t ldf,
+                      const float *__restrict__ Wc, TO *__restrict__ out, int64_t ldc, VSet vs)
+{
+    using X = XferShape<NF>;
+    constexpr int TPE = X::TPE, EPB = X::EPB, LDI = X::LDI, NPF = NF * NF * NF;
+    __shared__ float sJ[NF][NF];                // sJ[f][c] = J[f][c], c < nc
+    __shared__ float sv[EPB][NF][NF][LDI];      // [c][j][i] after the k contraction
+    __shared__ float sw[EPB][NF][NF][LDI];      // [c][b][i] after the j contraction
+    const int64_t v = vs.at(blockIdx.y);
+    r += v * ldf;
+    t += v * ldf;
+    out += v * ldc;
+    const int tid = threadIdx.x;
+    const int el = tid / TPE, ij = tid - el * TPE;
+    const int i = ij % NF, j = ij / NF;
+    const bool lane_ok = el < EPB;
+    if (tid < NF * nc) sJ[tid / nc][tid % nc] = J[tid];
+    const int ncc = nc * nc * nc;
+    const int64_t groups = (E + EPB - 1) / EPB;
+    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int64_t e = g * EPB + el;
+        const bool act = lane_ok && e < E;
+        __syncthreads();  // sJ ready; LDS of the previous group consumed
+        if (act) {
+            float sk[NF];
+#pragma unroll
+            for (int k = 0; k < NF; ++k) {
+                const int64_t p = e * NPF + k * TPE + ij;
+                sk[k] = W[p] * (r[p] - t[p]);
+            }
+#pragma unroll
+            for (int c = 0; c < NF; ++c) {
+                if (c < nc) {
+                    float a = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < NF; ++k) a += sJ[k][c] * sk[k];
+                    sv[el][c][j][i] = a;
+                }
+            }
+        }
+        __syncthreads();
+        if (act) {
+            for (int o = ij; o < nc * nc * NF; o += TPE) {
+                const int i2 = o % NF, b = (o / NF) % nc, c = o / (NF * nc);
+                float a = 0.0f;
+#pragma unroll
+                for (int jj = 0; jj < NF; ++jj) a += sJ[jj][b] * sv[el][c][jj][i2];
+                sw[el][c][b][i2] = a;
+            }
+        }
+        __syncthreads();
+        if (act) {
+            for (int o = ij; o < ncc; o += TPE) {
+                const int a0 = o % nc, b = (o / nc) % nc, c = o / (nc * nc);
+                float a = 0.0f;
+#pragma unroll
+                for (int ii = 0; ii < NF; ++ii) a += sJ[ii][a0] * sw[el][c][b][ii];
+                const int64_t q = e * ncc + o;
+                out[q] = Wc[q] > 0.0f ? (TO)a : TO(0);
+            }
+        }
+    }
+}
+
+template <int NF, typename TI>
+__global__ void __launch_bounds__(64)
+prolong_add_kernel(int64_t E, int nc, const float *__restrict__ J, const TI *__restrict__ in,
+                   int64_t ldc, float *__restrict__ x, int64_t ldf, VSet vs)
+{
+    using X = XferShape<NF>;
+    constexpr int TPE = X::TPE, EPB = X::EPB, LDI = X::LDI, NPF = NF * NF * NF;
+    __shared__ float sJ[NF][NF];             // sJ[f][c] = J[f][c], c < nc
+    __shared__ float se[EPB][NF * NF * NF];  // coarse values [c][b][a]
+    __shared__ float su[EPB][NF][NF][LDI];   // [c][b][i] after the a contraction
+    const int64_t v = vs.at(blockIdx.y);
+    in += v * ldc;
+    x += v * ldf;
+    const int tid = threadIdx.x;
+    const int el = tid / TPE, ij = tid - el * TPE;
+    const int i = ij % NF, j = ij / NF;
+    const bool lane_ok = el < EPB;
+    if (tid < NF * nc) sJ[tid / nc][tid % nc] = J[tid];
+    const int ncc = nc * nc * nc;
+    const int64_t groups = (E + EPB - 1) / EPB;
+    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int64_t e = g * EPB + el;
+        const bool act = lane_ok && e < E;
+        __syncthreads();
+        if (act)
+            for (int o = ij; o < ncc; o += TPE) se[el][o] = (float)in[e * ncc + o];
+        __syncthreads();
+        if (act) {
+            for (int o = ij; o < nc * nc * NF; o += TPE) {
+                const int i2 = o % NF, b = (o / NF) % nc, c = o / (NF * nc);
+                float a = 0.0f;
+                for (int aa = 0; aa < nc; ++aa) a += sJ[i2][aa] * se[el][aa + nc * (b + nc * c)];
+                su[el][c][b][i2] = a;
+            }
+        }
+        __syncthreads();
+        if (act) {
+            float u2[NF];
+#pragma unroll
+            for (int c = 0; c < NF; ++c) {
+                float a = 0.0f;
+                if (c < nc)
+                    for (int b = 0; b < nc; ++b) a += sJ[j][b] * su[el][c][b][i];
+                u2[c] = a;
+            }
+#pragma unroll
+            for (int k = 0; k < NF; ++k) {
+                float a = 0.0f;
+#pragma unroll
+                for (int c = 0; c < NF; ++c)
+                    if (c < nc) a += sJ[k][c] * u2[c];
+                const int64_t p = e * NPF + k * TPE + ij;
+                x[p] += a;
+            }
+        }
+    }
+}
+
+static int64_t xfer_grid(const Level &F)
+{
+    const int epb = 64 / (F.nq * F.nq);
+    const int64_t groups = (F.E + epb - 1) / epb;
+    const int64_t cap = (int64_t)(F.n_cu > 0 ? F.n_cu : 256) * 16;
+    return groups < cap ? groups : cap;
+}
+
+template <typename TO>
+int launch_restrict_resid(const Level &F, const Level &C, const float *r, const float *t, TO *out,
+                          const VSet &vs, hipStream_t s)
+{
+    if (vs.n <= 0) return SEM_OK;
+    if (F.nq > 8 || C.nq >= F.nq || C.E != F.E || !C.W32 || !F.W32 || !F.Jc32) {
+        set_error("restrict: unsupported level pair nq %d -> %d", F.nq, C.nq);
+        return SEM_EINVAL;
+    }
+    const dim3 grid((unsigned)xfer_grid(F), (unsigned)vs.n), block(64);
+#define SEM_RX(NF)                                                                          \
+    case NF:                                                                                \
+        hipLaunchKernelGGL((restrict_resid_kernel<NF, TO>), grid, block, 0, s, F.E, C.nq,   \
+                           F.Jc32, F.W32, r, t, F.nL, C.W32, out, C.nL, vs);                \
+        break
+    switch (F.nq) {
+        SEM_RX(2); SEM_RX(3); SEM_RX(4); SEM_RX(5); SEM_RX(6); SEM_RX(7); SEM_RX(8);
+    default: set_error("restrict: nq %d", F.nq); return SEM_EINVAL;
+    }
+#undef SEM_RX
+    SEM_HIP(hipGetLastError());
+    return SEM_OK;
+}
+
+template <typename TI>
+int launch_prolong_add(const Level &F, const Level &C, const TI *in, float *x, const VSet &vs,
+                       hipStream_t s)
+{
+    if (vs.n <= 0) return SEM_OK;
+    if (F.nq > 8 || C.nq >= F.nq || C.E != F.E || !F.Jc32) {
+        set_error("prolong: unsupported level pair nq %d -> %d", C.nq, F.nq);
+        return SEM_EINVAL;
+    }
+    const dim3 grid((unsigned)xfer_grid(F), (unsigned)vs.n), block(64);
+#define SEM_PX(NF)                                                                          \
+    case NF:                                                                                \
+        hipLaunchKernelGGL((prolong_add_kernel<NF, TI>), grid, block, 0, s, F.E, C.nq,      \
+                           F.Jc32, in, C.nL, x, F.nL, vs);                                  \
+        break
+    switch (F.nq) {
+        SEM_PX(2); SEM_PX(3); SEM_PX(4); SEM_PX(5); SEM_PX(6); SEM_PX(7); SEM_PX(8);
+    default: set_error("prolong: nq %d", F.nq); return SEM_EINVAL;
+    }
+#undef SEM_PX
+    SEM_HIP(hipGetLastError());
+    return SEM_OK;
+}
+template int launch_restrict_resid<float>(const Level &, const Level &, const float *, const float *,
+                                          float *, const VSet &, hipStream_t);
+template int launch_restrict_resid<double>(const Level &, const Level &, const float *, const float *,
+                                           double *, const VSet &, hipStream_t);
+template int launch_prolong_add<float>(const Level &, const Level &, const float *, float *,
+                                       const VSet &, hipStream_t);
+template int launch_prolong_add<double>(const Level &, const Level &, const double *, float *,
+                                        const VSet &, hipStream_t);
+
 }  // namespace semx

@@ -112,7 +112,6 @@ struct Level {
     int64_t *gid = nullptr;
     uint8_t *dir = nullptr;
     int32_t *perm = nullptr, *offs = nullptr;
-    int32_t *segid = nullptr;  // per copy: segment of its node in perm, -1 if unshared
     // wavefront chunks of whole segments for the gather-scatter kernel
     int64_t nchunks = 0, nover = 0;
     int32_t *chunk_b = nullptr, *chunk_e = nullptr;  // perm range of each chunk
@@ -214,6 +213,16 @@ int launch_grad_k(const Level &L, const double *u, const double *lam, double h1,
 template <typename T>
 int launch_interp(int64_t E, int ns, int nt, const T *J, const T *in, T *out, bool transpose,
                   hipStream_t s);
+
+// fused p-multigrid transfers between smoother level F (nq <= 8) and the next
+// coarser level C for a batch of vectors (fine arrays [nv][F.nL], coarse
+// [nv][C.nL]): out = mask_C (J^T)^3 [W_F (r - t)] and x += J^3 in
+template <typename TO>
+int launch_restrict_resid(const Level &F, const Level &C, const float *r, const float *t, TO *out,
+                          const VSet &vs, hipStream_t s);
+template <typename TI>
+int launch_prolong_add(const Level &F, const Level &C, const TI *in, float *x, const VSet &vs,
+                       hipStream_t s);
 
 // setup helpers
 int build_maps(Level &L, const int64_t *gid_dev, const uint8_t *dir_dev, const double *x,

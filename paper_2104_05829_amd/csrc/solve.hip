@@ -129,21 +129,25 @@ __global__ void dot_kernel(int64_t n, const double *__restrict__ W, const double
 
 // ---------------------------------------------------------------- Jacobi-PCG
 // r = b - Ax (Ax may be null: x = 0), p = Dinv r; partials (W r p, W r r, W b b)
+// r32 (nullable): FP32 copy of r, the p-multigrid input
 __global__ void pcg_init_kernel(int64_t n, VSet vs, int64_t ldb, const double *__restrict__ b,
                                 int64_t ld, const double *__restrict__ Ax,
                                 const double *__restrict__ Dinv, const double *__restrict__ W,
                                 double *__restrict__ r, double *__restrict__ p,
-                                double *__restrict__ partial, int64_t pst, int precondition)
+                                float *__restrict__ r32, double *__restrict__ partial, int64_t pst,
+                                int precondition)
 {
     const int64_t v = vsel(vs);
     b += v * ldb;
     if (Ax) Ax += v * ld;
     r += v * ld;
     if (p) p += v * ld;
+    if (r32) r32 += v * ld;
     double s[3] = {0.0, 0.0, 0.0};
     GRID_LOOP(i, n) {
         const double ri = b[i] - (Ax ? Ax[i] : 0.0);
         r[i] = ri;
+        if (r32) r32[i] = (float)ri;
         const double zi = precondition ? Dinv[i] * ri : ri;
         if (p) p[i] = zi;
         const double wi = W[i];
@@ -261,14 +265,15 @@ __global__ void pcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars
 }
 
 // flexible-CG update: alpha from the operator partials, x += alpha p,
-// r -= alpha QQ^T(A_L p); partial (W r r)
+// r -= alpha QQ^T(A_L p), r32 = FP32 copy of r (the V-cycle input);
+// partial (W r r)
 __global__ void fcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t ldx,
                                         KrylovScalars *sc, int parity,
                                         const double *__restrict__ pax, int64_t pst_ax, int64_t nbax,
                                         const double *__restrict__ p, const double *__restrict__ w,
                                         const double *__restrict__ W, double *__restrict__ x,
-                                        double *__restrict__ r, double *__restrict__ partial,
-                                        int64_t pst)
+                                        double *__restrict__ r, float *__restrict__ r32,
+                                        double *__restrict__ partial, int64_t pst)
 {
     const int64_t v = vsel(vs);
     sc += v;
@@ -276,6 +281,7 @@ __global__ void fcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t 
     p += v * ld;
     w += v * ld;
     r += v * ld;
+    r32 += v * ld;
     x += v * ldx;
     double res[1];
     sum_partials<1>(pax + v * pst_ax, nbax, res);
@@ -298,14 +304,16 @@ __global__ void fcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t 
         x[i] += a * p[i];
         const double ri = r[i] - a * w[i];
         r[i] = ri;
+        r32[i] = (float)ri;
         s[0] += W[i] * ri * ri;
     }
     block_sum_store<1>(s, partial + v * pst);
 }
 
-// (z, w)_W and (z, r)_W for assembled w
+// (z, w)_W and (z, r)_W for assembled w, z the FP32 V-cycle output taken to
+// FP64 (W = 0 on Dirichlet copies applies the restriction)
 __global__ void dot_zw_kernel(int64_t n, VSet vs, int64_t ld, const KrylovScalars *sc,
-                              const double *__restrict__ W, const double *__restrict__ z,
+                              const double *__restrict__ W, const float *__restrict__ z,
                               const double *__restrict__ wa, const double *__restrict__ r,
                               double *__restrict__ partial, int64_t pst)
 {
@@ -316,7 +324,7 @@ __global__ void dot_zw_kernel(int64_t n, VSet vs, int64_t ld, const KrylovScalar
     r += v * ld;
     double s[2] = {0.0, 0.0};
     GRID_LOOP(i, n) {
-        const double wz = W[i] * z[i];
+        const double wz = W[i] * (double)z[i];
         s[0] += wz * wa[i];
         s[1] += wz * r[i];
     }
@@ -325,10 +333,12 @@ __global__ void dot_zw_kernel(int64_t n, VSet vs, int64_t ld, const KrylovScalar
 
 // Polak-Ribiere direction update, beta = (z_new, r_new - r_old) / (z_old, r_old)
 // = -alpha (z_new, A p) / rz_old (r_new - r_old = -alpha A p), taken by every
-// block from the partials of dot_zw_kernel; first = 1 gives p = z.
+// block from the partials of dot_zw_kernel; first = 1 gives p = z.  z is the
+// FP32 V-cycle output, zero on Dirichlet copies (mask W32 > 0).
 __global__ void fcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars *sc, int parity,
                                    const double *__restrict__ pz, int64_t pst, int64_t nbz,
-                                   const double *__restrict__ z, double *__restrict__ p, int first)
+                                   const float *__restrict__ z, const float *__restrict__ W32,
+                                   double *__restrict__ p, int first)
 {
     const int64_t v = vsel(vs);
     sc += v;
@@ -351,7 +361,7 @@ __global__ void fcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars
         }
     }
     if (bad) return;
-    GRID_LOOP(i, n) p[i] = z[i] + be * p[i];
+    GRID_LOOP(i, n) p[i] = (W32[i] > 0.0f ? (double)z[i] : 0.0) + be * p[i];
 }
 
 // Chebyshev step on assembled t = QQ^T A_L x (t null when x = 0):
@@ -556,7 +566,8 @@ static int ensure_workspace(sem_handle h, bool pmg, int nv)
                 SEM_HIP(hipMalloc(&w.mg_x[l], sizeof(float) * m));
                 SEM_HIP(hipMalloc(&w.mg_t[l], sizeof(float) * m));
                 SEM_HIP(hipMalloc(&w.mg_d[l], sizeof(float) * m));
-                SEM_HIP(hipMalloc(&w.mg_s[l], sizeof(float) * m));
+                if (h->lv[l].nq > 8)  // unfused transfers stage the residual here
+                    SEM_HIP(hipMalloc(&w.mg_s[l], sizeof(float) * m));
             }
             const int lc = h->n_levels - 1;
             const int64_t m = h->lv[lc].nL * nvn;
@@ -782,8 +793,8 @@ static int pcg_start(sem_handle h, const Level &L, const VSet &vs, const double 
         SEM_TRY(launch_gs_multi<double>(L, kv.w, n, vs, s, nullptr, 0));
         Ax = kv.w;
     }
-    LAUNCH_B(pcg_init_kernel, n, vs, s, n, vs, ldb, b, n, Ax, L.Dinv, L.W, kv.r, kv.p, ws.partial,
-             ws.pst, 1);
+    LAUNCH_B(pcg_init_kernel, n, vs, s, n, vs, ldb, b, n, Ax, L.Dinv, L.W, kv.r, kv.p,
+             (float *)nullptr, ws.partial, ws.pst, 1);
     LAUNCH_1B(fin_init_kernel, vs, s, vs, (const double *)ws.partial, ws.pst, (int64_t)red_grid(n),
               kv.sc, tol, maxit);
     return SEM_OK;
@@ -812,63 +823,69 @@ static int vcycle(sem_handle h, int l, const VSet &vs, const SolveCfg &cfg, hipS
     // pre-smoothing from x = 0
     SEM_TRY(chebyshev(L, l, h, vs, r, x, true, lmin_f * lmax, lmax_f * lmax, cfg.deg, cfg.h1,
                       cfg.h2, s));
-    // restricted residual s = W (r - A x)
+    // restricted residual s = W (r - A x), coarse-grid correction x += J e_c
     SEM_TRY(apply_f32(L, vs, x, t, cfg.h1, cfg.h2, s));
-    LAUNCH_B(wresid_fused_kernel, n, vs, s, n, vs, n, L.W32, (const float *)r, (const float *)t,
-             sres);
     const Level &C = h->lv[l + 1];
     const int64_t nc = C.nL;
-    if (l + 1 == lc) {
-        // restrict in FP32 into the head of t (n >= nc), then FP64 for the coarse solve
-        double *bc = (double *)w.mg_r[l + 1];
-        for (int q = 0; q < vs.n; ++q) {
-            const int64_t v = vs.at(q);
-            SEM_TRY(launch_interp<float>(L.E, L.nq, C.nq, L.Jc32, sres + v * n, t + v * n, true, s));
+    const bool coarsest = l + 1 == lc;  // FP64 coarse solve below
+    if (L.nq <= 8) {
+        // fused transfers (residual and mask into the restriction, the
+        // correction added inside the prolongation)
+        if (coarsest) {
+            double *bc = (double *)w.mg_r[l + 1];
+            SEM_TRY(launch_restrict_resid<double>(L, C, r, t, bc, vs, s));
+            SEM_TRY(launch_gs_multi<double>(C, bc, nc, vs, s, nullptr, 0));
+        } else {
+            float *rc = (float *)w.mg_r[l + 1];
+            SEM_TRY(launch_restrict_resid<float>(L, C, r, t, rc, vs, s));
+            SEM_TRY(launch_gs_multi<float>(C, rc, nc, vs, s, nullptr, 0));
         }
-        LAUNCH_B((convert_kernel<float, double>), nc, vs, s, nc, vs, n, (const float *)t, nc, bc);
-        SEM_TRY(launch_gs_multi<double>(C, bc, nc, vs, s, nullptr, 0));
-        LAUNCH_B((mask_kernel<double, double>), nc, vs, s, nc, vs, nc, C.W, bc);
         SEM_TRY(vcycle(h, l + 1, vs, cfg, s));
-        LAUNCH_B((convert_kernel<double, float>), nc, vs, s, nc, vs, nc,
-                 (const double *)w.mg_x[l + 1], n, t);
-        // prolong: x += J e_c  (sres reused for the fine-sized interpolant)
-        for (int q = 0; q < vs.n; ++q) {
-            const int64_t v = vs.at(q);
-            SEM_TRY(launch_interp<float>(L.E, C.nq, L.nq, L.Jc32, t + v * n, sres + v * n, false, s));
-        }
+        if (coarsest)
+            SEM_TRY(launch_prolong_add<double>(L, C, (const double *)w.mg_x[l + 1], x, vs, s));
+        else
+            SEM_TRY(launch_prolong_add<float>(L, C, (const float *)w.mg_x[l + 1], x, vs, s));
     } else {
-        float *rc = (float *)w.mg_r[l + 1];
-        for (int q = 0; q < vs.n; ++q) {
-            const int64_t v = vs.at(q);
-            SEM_TRY(launch_interp<float>(L.E, L.nq, C.nq, L.Jc32, sres + v * n, rc + v * nc, true, s));
+        LAUNCH_B(wresid_fused_kernel, n, vs, s, n, vs, n, L.W32, (const float *)r, (const float *)t,
+                 sres);
+        if (coarsest) {
+            // restrict in FP32 into the head of t (n >= nc), then FP64 for the coarse solve
+            double *bc = (double *)w.mg_r[l + 1];
+            for (int q = 0; q < vs.n; ++q) {
+                const int64_t v = vs.at(q);
+                SEM_TRY(launch_interp<float>(L.E, L.nq, C.nq, L.Jc32, sres + v * n, t + v * n, true, s));
+            }
+            LAUNCH_B((convert_kernel<float, double>), nc, vs, s, nc, vs, n, (const float *)t, nc, bc);
+            SEM_TRY(launch_gs_multi<double>(C, bc, nc, vs, s, nullptr, 0));
+            LAUNCH_B((mask_kernel<double, double>), nc, vs, s, nc, vs, nc, C.W, bc);
+            SEM_TRY(vcycle(h, l + 1, vs, cfg, s));
+            LAUNCH_B((convert_kernel<double, float>), nc, vs, s, nc, vs, nc,
+                     (const double *)w.mg_x[l + 1], n, t);
+            // prolong: sres = J e_c (sres reused for the fine-sized interpolant)
+            for (int q = 0; q < vs.n; ++q) {
+                const int64_t v = vs.at(q);
+                SEM_TRY(launch_interp<float>(L.E, C.nq, L.nq, L.Jc32, t + v * n, sres + v * n, false, s));
+            }
+        } else {
+            float *rc = (float *)w.mg_r[l + 1];
+            for (int q = 0; q < vs.n; ++q) {
+                const int64_t v = vs.at(q);
+                SEM_TRY(launch_interp<float>(L.E, L.nq, C.nq, L.Jc32, sres + v * n, rc + v * nc, true, s));
+            }
+            SEM_TRY(launch_gs_multi<float>(C, rc, nc, vs, s, nullptr, 0));
+            LAUNCH_B((mask_kernel<float, float>), nc, vs, s, nc, vs, nc, C.W32, rc);
+            SEM_TRY(vcycle(h, l + 1, vs, cfg, s));
+            const float *xc = (const float *)w.mg_x[l + 1];
+            for (int q = 0; q < vs.n; ++q) {
+                const int64_t v = vs.at(q);
+                SEM_TRY(launch_interp<float>(L.E, C.nq, L.nq, L.Jc32, xc + v * nc, sres + v * n, false, s));
+            }
         }
-        SEM_TRY(launch_gs_multi<float>(C, rc, nc, vs, s, nullptr, 0));
-        LAUNCH_B((mask_kernel<float, float>), nc, vs, s, nc, vs, nc, C.W32, rc);
-        SEM_TRY(vcycle(h, l + 1, vs, cfg, s));
-        const float *xc = (const float *)w.mg_x[l + 1];
-        for (int q = 0; q < vs.n; ++q) {
-            const int64_t v = vs.at(q);
-            SEM_TRY(launch_interp<float>(L.E, C.nq, L.nq, L.Jc32, xc + v * nc, sres + v * n, false, s));
-        }
+        LAUNCH_B(add_kernel<float>, n, vs, s, n, vs, n, (const float *)sres, x);
     }
-    LAUNCH_B(add_kernel<float>, n, vs, s, n, vs, n, (const float *)sres, x);
     // post-smoothing
     SEM_TRY(chebyshev(L, l, h, vs, r, x, false, lmin_f * lmax, lmax_f * lmax, cfg.deg, cfg.h1,
                       cfg.h2, s));
-    return SEM_OK;
-}
-
-// z = M(r) for the batch vs: V-cycle on the FP64 fine residuals
-static int precondition_pmg(sem_handle h, const VSet &vs, const double *r, double *z,
-                            const SolveCfg &cfg, hipStream_t s)
-{
-    Workspace &w = h->ws;
-    const Level &F = h->lv[0];
-    const int64_t n = F.nL;
-    LAUNCH_B((convert_kernel<double, float>), n, vs, s, n, vs, n, r, n, (float *)w.mg_r[0]);
-    SEM_TRY(vcycle(h, 0, vs, cfg, s));
-    LAUNCH_B((convert_kernel<float, double>), n, vs, s, n, vs, n, (const float *)w.mg_x[0], n, z);
-    LAUNCH_B((mask_kernel<double, double>), n, vs, s, n, vs, n, F.W, z);
     return SEM_OK;
 }
 
@@ -905,7 +922,7 @@ static int true_residual(sem_handle h, const VSet &vs, const double *k, double h
     SEM_TRY(launch_gs_multi<double>(F, w.w, n, vs, s, nullptr, 0));
     // pcg_init computes (W r r, W b b) for r = b - Ax
     LAUNCH_B(pcg_init_kernel, n, vs, s, n, vs, ld, b, n, (const double *)w.w, F.Dinv, F.W, w.z,
-             (double *)nullptr, w.partial, w.pst, 0);
+             (double *)nullptr, (float *)nullptr, w.partial, w.pst, 0);
     const int nb = red_grid(n);
     std::vector<double> hp((size_t)3 * nb * vs.n);
     for (int q = 0; q < vs.n; ++q)
@@ -1004,8 +1021,9 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
             SEM_TRY(launch_gs_multi<double>(F, w.w, n, all, s, nullptr, 0));
             Ax = w.w;
         }
+        float *r32 = (float *)w.mg_r[0], *z32 = (float *)w.mg_x[0];  // V-cycle input, output
         LAUNCH_B(pcg_init_kernel, n, all, s, n, all, ld, b, n, Ax, F.Dinv, F.W, w.r,
-                 (double *)nullptr, w.partial, w.pst, 0);
+                 (double *)nullptr, r32, w.partial, w.pst, 0);
         LAUNCH_1B(fin_init_kernel, all, s, all, (const double *)w.partial, w.pst,
                   (int64_t)red_grid(n), w.sc, o->tol, o->maxit);
         SEM_TRY(read_scalars(h, false, s));
@@ -1014,11 +1032,11 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
         const int *skip = &w.sc[0].done;
         VSet cycled{0, 0u};  // vectors whose coarse counts are still to be read
         if (act.n > 0) {
-            SEM_TRY(precondition_pmg(h, act, w.r, w.z, cfg, s));
+            SEM_TRY(vcycle(h, 0, act, cfg, s));
             LAUNCH_B(dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
-                     (const double *)w.z, (const double *)w.r, (const double *)w.r, w.partial, w.pst);
+                     (const float *)z32, (const double *)w.r, (const double *)w.r, w.partial, w.pst);
             LAUNCH_B(fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, 1, (const double *)w.partial,
-                     w.pst, (int64_t)nbv, (const double *)w.z, w.p, 1);
+                     w.pst, (int64_t)nbv, (const float *)z32, F.W32, w.p, 1);
             cycled = act;
         }
         for (int it = 0; act.n > 0; ++it) {
@@ -1030,7 +1048,7 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
             SEM_TRY(launch_gs_multi<double>(F, w.w, n, act, s, skip, kScStride));
             LAUNCH_B(fcg_update_fused_kernel, n, act, s, n, act, n, ld, w.sc, parity,
                      (const double *)w.partial_ax, w.pst_ax, nbax, (const double *)w.p,
-                     (const double *)w.w, F.W, x, w.r, w.partial, w.pst);
+                     (const double *)w.w, F.W, x, w.r, r32, w.partial, w.pst);
             LAUNCH_1B(fin_conv_kernel, act, s, act, (const double *)w.partial, w.pst, (int64_t)nbv,
                       w.sc);
             // one host synchronisation per iteration: outer scalars, and the
@@ -1041,11 +1059,12 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
             cycled = VSet{0, 0u};
             act = live_set(w, act);
             if (act.n == 0) break;
-            SEM_TRY(precondition_pmg(h, act, w.r, w.z, cfg, s));
+            SEM_TRY(vcycle(h, 0, act, cfg, s));
             LAUNCH_B(dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
-                     (const double *)w.z, (const double *)w.w, (const double *)w.r, w.partial, w.pst);
+                     (const float *)z32, (const double *)w.w, (const double *)w.r, w.partial, w.pst);
             LAUNCH_B(fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, parity,
-                     (const double *)w.partial, w.pst, (int64_t)nbv, (const double *)w.z, w.p, 0);
+                     (const double *)w.partial, w.pst, (int64_t)nbv, (const float *)z32, F.W32, w.p,
+                     0);
             cycled = act;
         }
     }
