@@ -14,6 +14,8 @@ Also reported on the same JSON line:
                 bounded sample of the same workload
   ax_three_fields  sem_ax_multi on three fields of the same mesh (the
                 geometric factors read once for all three)
+  projection    a sequence of slowly varying loads solved from zero and with
+                initial guesses projected onto earlier solutions
   pcg           time to a true relative residual of 1e-8 on the 32^3 deformed
                 Helmholtz box (h1=1, h2=10, N=7, 3 Gaussian right-hand sides):
                 FCG with the FP32 p-multigrid (7->3->1) against FP64 Jacobi-PCG,
@@ -201,6 +203,38 @@ def bench_pcg(args, torch, sem_mod, inputs):
     if "jacobi" in out:
         out["gdof_per_s_per_iter_jacobi"] = round(
             inf["n_unique"] * sum(out["jacobi"]["iters"]) / (out["jacobi"]["ms_total"] * 1e-3) / 1e9, 3)
+    return out
+
+
+def bench_projection(args, torch, sem_mod, inputs):
+    """A sequence of 10 slowly varying loads (inputs.load_sequence, seed 60,
+    period 40, eps 1e-3) on the 32^3 deformed Helmholtz box, FCG + FP32 p-MG to 1e-8:
+    from zero against projected initial guesses onto up to 8 earlier
+    solutions (cleared first)."""
+    N, ne, steps = 7, args.pcg_elems, 10
+    mesh = sem_mod.box_mesh(ne, ne, ne, N, deform="cyclic", amp=0.05, bc="dirichlet")
+    s = sem_mod.Sem(mesh, levels=(7, 3, 1))
+    loads = [torch.tensor(f, device="cuda") for f in inputs.load_sequence(mesh.gid, steps, 60, 40.0)]
+    kw = dict(tol=1e-8, h1=1.0, h2=10.0, precond="pmg", coarse_tol=args.coarse_tol,
+              coarse_maxit=args.coarse_maxit)
+    s.solve(s.rhs(loads[0]), **kw)  # preconditioner setup
+    out = {"workload": f"{ne}x{ne}x{ne} deformed box, N=7, Helmholtz h1=1 h2=10, sequence of {steps} "
+                       "loads f_n = g0 + sin(2 pi n/40) g1 + (n/40)^2 g2 + 1e-3 h_n, p-MG to 1e-8"}
+    for label, L in (("from_zero", 0), ("projected_L8", 8)):
+        s.proj_reset()
+        its, rels, ms = [], [], 0.0
+        for f in loads:
+            b = s.rhs(f)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st, rc = s.solve(b, proj_dim=L, **kw)
+            torch.cuda.synchronize()
+            ms += (time.perf_counter() - t0) * 1e3
+            its.append(st["iters"])
+            rels.append(float(f"{st['true_rel_res']:.3e}"))
+        out[label] = {"ms_total": round(ms, 3), "iters": its, "true_rel_res_max": max(rels)}
+    out["speedup"] = round(out["from_zero"]["ms_total"] / out["projected_L8"]["ms_total"], 3)
+    s.free()
     return out
 
 
@@ -474,6 +508,9 @@ def main():
     if not args.no_pcg:
         log("[bench] pcg: 32^3 Helmholtz, FCG+FP32 p-MG vs FP64 Jacobi-PCG to 1e-8")
         line["pcg"] = bench_pcg(args, torch, sem_mod, inputs)
+    if not args.no_pcg:
+        log("[bench] projection: 10-load sequence, p-MG from zero vs projected guesses")
+        line["projection"] = bench_projection(args, torch, sem_mod, inputs)
     if not args.no_small:
         log("[bench] 4^3 Poisson Jacobi-PCG and 8^3 adjoint")
         line["c1"] = bench_c1(args, torch, sem_mod, inputs, not args.no_cpu)

@@ -63,6 +63,8 @@ enum sem_dtype { SEM_F64 = 0, SEM_F32 = 1 };
 /* Largest number of right-hand sides sem_pcg_solve_multi takes in one call
  * (and the batch size in which sem_ax_multi / sem_gs_multi process theirs). */
 #define SEM_MAX_RHS 4
+/* Largest projection space (earlier solutions kept per right-hand-side slot). */
+#define SEM_MAX_PROJ 16
 enum sem_precond { SEM_PRECOND_JACOBI = 0, SEM_PRECOND_PMG = 1 };
 
 /*
@@ -175,6 +177,9 @@ typedef struct {
     double coarse_tol;   /* coarsest-level Jacobi-PCG relative tolerance */
     int coarse_maxit;
     int zero_guess;      /* 1: ignore x on entry and start from 0 */
+    int proj_dim;        /* 0: off; L in 1..SEM_MAX_PROJ: initial guess projected onto
+                            up to L earlier solutions (see sem_proj_reset); x on entry
+                            is then ignored; constant coefficients only (k = NULL) */
 } sem_solve_opts;
 
 typedef struct {
@@ -185,12 +190,14 @@ typedef struct {
     double ms_solve;       /* wall time of the iteration (host clock) */
     double ms_setup;       /* preconditioner setup done inside this call */
     int coarse_iters;      /* total coarsest-level iterations (PMG) */
+    int proj_vectors;      /* earlier solutions the initial guess was projected onto */
+    double proj_rel_res;   /* ||b - A xbar||_W / ||b||_W of the projected guess xbar */
 } sem_solve_stats;
 
 /* Fill opts with defaults: h1 = 1, h2 = 0, k = NULL, tol = 1e-8, maxit = 1000,
  * Jacobi, check_every = 8, cheb_degree = 2, lanczos_steps = 20,
  * interval [0.1, 1.1] lambda_max, coarse_tol = 1e-2, coarse_maxit = 20,
- * zero_guess = 1. */
+ * zero_guess = 1, proj_dim = 0. */
 SEM_API void sem_solve_opts_default(sem_solve_opts *opts);
 
 /*
@@ -210,6 +217,21 @@ SEM_API void sem_solve_opts_default(sem_solve_opts *opts);
  */
 SEM_API int sem_pcg_solve(sem_handle h, const double *b, double *x, const sem_solve_opts *opts,
                   sem_solve_stats *stats, void *stream);
+
+/*
+ * Projection of initial guesses for successive right-hand sides (the pressure
+ * initial guesses of Sec. 3.4 / Sec. 4, after Fischer, CMAME 163, 1998).  With
+ * opts->proj_dim = L > 0 every solve keeps, per right-hand-side slot (slot 0
+ * for sem_pcg_solve, slot r for row r of sem_pcg_solve_multi), up to L earlier
+ * solution increments xt_i, orthonormal in the A inner product, and A xt_i:
+ *   xbar = sum_i (xt_i, b)_W xt_i  (the A-norm best guess from the space),
+ *   solve A dx = b - A xbar from zero to ||r||_W <= tol ||b||_W,  x = xbar + dx,
+ * then dx, A-orthogonalised and A-normalised, joins the space, or the space
+ * restarts from x / ||x||_A once it holds L vectors.  Spaces belong to the
+ * handle's operator (h1, h2) and are cleared when h1, h2 or L change, or by
+ * this call (all slots).  Device memory: 2 L n_local doubles per slot used.
+ */
+SEM_API int sem_proj_reset(sem_handle h);
 
 /*
  * nrhs independent solves with one operator, advanced in lockstep so that

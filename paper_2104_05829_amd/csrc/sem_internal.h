@@ -37,6 +37,8 @@ constexpr int kMaxLevels = 4;
 // largest number of vectors one batched operator / gather-scatter / solve
 // call processes together
 constexpr int kMaxRhs = SEM_MAX_RHS;
+// largest projection space (earlier solutions kept per right-hand-side slot)
+constexpr int kMaxProj = SEM_MAX_PROJ;
 
 // A batch of vectors v = idx(0) .. idx(n-1) of an array with leading
 // dimension ld (vector v starts at base + v * ld); indices packed 8 bits each.
@@ -149,6 +151,16 @@ struct Workspace {
     void *mg_r[kMaxLevels] = {}, *mg_x[kMaxLevels] = {}, *mg_t[kMaxLevels] = {},
          *mg_d[kMaxLevels] = {}, *mg_s[kMaxLevels] = {};
     double *c_r = nullptr, *c_p = nullptr, *c_w = nullptr;  // coarse CG
+    // projection of initial guesses: per right-hand-side slot, l A-orthonormal
+    // vectors xt [L][nL] and bt = A xt [L][nL]; projected guess and remainder
+    // right-hand side of the current solve [nv_proj][nL]
+    struct Proj {
+        double *xt = nullptr, *bt = nullptr;
+        int l = 0;
+    } proj[kMaxRhs];
+    int proj_L = 0, proj_nv = 0;
+    double proj_h1 = 0.0, proj_h2 = 0.0;
+    double *proj_xb = nullptr, *proj_bp = nullptr;
 };
 
 struct PrecondKey {

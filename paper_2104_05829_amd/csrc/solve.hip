@@ -158,14 +158,22 @@ __global__ void pcg_init_kernel(int64_t n, VSet vs, int64_t ldb, const double *_
     block_sum_store<3>(s, partial + v * pst);
 }
 
+// reference (b, b)_W per vector for the stopping test (0: that of the
+// right-hand side being solved); set when the system solved is the remainder
+// of a projected guess and the tolerance stays relative to the original b
+struct BbRef {
+    double v[kMaxRhs];
+};
+
 // one block per vector
 __global__ void fin_init_kernel(VSet vs, const double *partial, int64_t pst, int64_t nb,
-                                KrylovScalars *sc, double tol, int maxit)
+                                KrylovScalars *sc, double tol, int maxit, BbRef ref)
 {
     const int64_t v = vsel(vs);
     sc += v;
     double res[3];
     sum_partials<3>(partial + v * pst, nb, res);
+    if (ref.v[v] > 0.0) res[2] = ref.v[v];
     if (threadIdx.x == 0) {
         sc->rz = res[0];
         sc->rz_old = res[0];
@@ -428,6 +436,55 @@ __global__ void add_kernel(int64_t n, VSet vs, int64_t ld, const T *__restrict__
     GRID_LOOP(i, n) y[i] += a[i];
 }
 
+// ------------------------------------------------------------- projection
+struct Coefs {
+    double c[kMaxProj];
+};
+
+// partial sums of (W a, y_q) for q < m, y_q = Y + q * ldY (kMaxProj records
+// per block, the first m used)
+__global__ void wdots_kernel(int64_t n, const double *__restrict__ W, const double *__restrict__ a,
+                             const double *__restrict__ Y, int64_t ldY, int m,
+                             double *__restrict__ partial)
+{
+    double s[kMaxProj];
+#pragma unroll
+    for (int q = 0; q < kMaxProj; ++q) s[q] = 0.0;
+    GRID_LOOP(i, n) {
+        const double wa = W[i] * a[i];
+#pragma unroll
+        for (int q = 0; q < kMaxProj; ++q)
+            if (q < m) s[q] += wa * Y[q * ldY + i];
+    }
+    block_sum_store<kMaxProj>(s, partial);
+}
+
+// out = c0 base + sum_{q < m} c_q y_q  (base nullable; out may be base)
+__global__ void lincomb_kernel(int64_t n, const double *base, double c0,
+                               const double *__restrict__ Y, int64_t ldY, int m, Coefs c,
+                               double *out)
+{
+    GRID_LOOP(i, n) {
+        double acc = base ? c0 * base[i] : 0.0;
+#pragma unroll
+        for (int q = 0; q < kMaxProj; ++q)
+            if (q < m) acc += c.c[q] * Y[q * ldY + i];
+        out[i] = acc;
+    }
+}
+
+// out = c0 a0 + c1 a1 + c2 a2 (a1, a2 nullable; out may alias any input)
+__global__ void lincomb3_kernel(int64_t n, const double *a0, double c0, const double *a1, double c1,
+                                const double *a2, double c2, double *out)
+{
+    GRID_LOOP(i, n) {
+        double acc = c0 * a0[i];
+        if (a1) acc += c1 * a1[i];
+        if (a2) acc += c2 * a2[i];
+        out[i] = acc;
+    }
+}
+
 // ---------------------------------------------------------- load / adjoint
 // y = B o x (mass-weighted copy)
 __global__ void mass_kernel(int64_t n, const double *__restrict__ B, const double *__restrict__ x,
@@ -514,10 +571,24 @@ static void free_vectors(Workspace &w)
     w.pmg = false;
 }
 
+static void free_projection(Workspace &w)
+{
+    for (int v = 0; v < kMaxRhs; ++v) {
+        if (w.proj[v].xt) (void)hipFree(w.proj[v].xt);
+        if (w.proj[v].bt) (void)hipFree(w.proj[v].bt);
+        w.proj[v] = Workspace::Proj{};
+    }
+    if (w.proj_xb) (void)hipFree(w.proj_xb);
+    if (w.proj_bp) (void)hipFree(w.proj_bp);
+    w.proj_xb = w.proj_bp = nullptr;
+    w.proj_L = w.proj_nv = 0;
+}
+
 void free_workspace(sem_handle h)
 {
     Workspace &w = h->ws;
     free_vectors(w);
+    free_projection(w);
     void *ptrs[] = {w.aux, w.partial, w.partial_ax, w.sc, w.sc_c};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -542,7 +613,8 @@ static int ensure_workspace(sem_handle h, bool pmg, int nv)
         // vector-kernel partials: at most kMaxRedBlocks records of 3 per
         // vector; operator partials: one per workgroup of the persistent grid
         w.pst = 3 * kMaxRedBlocks;
-        SEM_HIP(hipMalloc(&w.partial, sizeof(double) * w.pst * kMaxRhs));
+        SEM_HIP(hipMalloc(&w.partial, sizeof(double) * std::max<int64_t>(w.pst * kMaxRhs,
+                                                                         (int64_t)kMaxProj * kMaxRedBlocks)));
         w.pst_ax = (int64_t)(F.n_cu > 0 ? F.n_cu : 256) * kAxMaxBlocksPerCU + 64;
         SEM_HIP(hipMalloc(&w.partial_ax, sizeof(double) * w.pst_ax * kMaxRhs));
         SEM_HIP(hipMalloc(&w.sc, sizeof(KrylovScalars) * kMaxRhs));
@@ -779,7 +851,7 @@ static int pcg_iterations(sem_handle h, const Level &L, const VSet &vs, const do
 // start a Jacobi-PCG on level L for the batch vs: x given (Ax computed) or zero
 static int pcg_start(sem_handle h, const Level &L, const VSet &vs, const double *k, double h1,
                      double h2, const double *b, int64_t ldb, const KrylovVecs &kv, bool zero,
-                     double tol, int maxit, hipStream_t s)
+                     double tol, int maxit, const BbRef &ref, hipStream_t s)
 {
     Workspace &ws = h->ws;
     const int64_t n = L.nL;
@@ -796,7 +868,7 @@ static int pcg_start(sem_handle h, const Level &L, const VSet &vs, const double 
     LAUNCH_B(pcg_init_kernel, n, vs, s, n, vs, ldb, b, n, Ax, L.Dinv, L.W, kv.r, kv.p,
              (float *)nullptr, ws.partial, ws.pst, 1);
     LAUNCH_1B(fin_init_kernel, vs, s, vs, (const double *)ws.partial, ws.pst, (int64_t)red_grid(n),
-              kv.sc, tol, maxit);
+              kv.sc, tol, maxit, ref);
     return SEM_OK;
 }
 
@@ -812,7 +884,7 @@ static int vcycle(sem_handle h, int l, const VSet &vs, const SolveCfg &cfg, hipS
         double *b = (double *)w.mg_r[l];
         const KrylovVecs kv{(double *)w.mg_x[l], n, w.c_r, w.c_p, w.c_w, w.sc_c};
         SEM_TRY(pcg_start(h, L, vs, nullptr, cfg.h1, cfg.h2, b, n, kv, true, cfg.coarse_tol,
-                          cfg.coarse_maxit, s));
+                          cfg.coarse_maxit, BbRef{}, s));
         SEM_TRY(pcg_iterations(h, L, vs, nullptr, cfg.h1, cfg.h2, kv, 1, cfg.coarse_maxit, s));
         return SEM_OK;
     }
@@ -941,6 +1013,146 @@ static int true_residual(sem_handle h, const VSet &vs, const double *k, double h
     return SEM_OK;
 }
 
+// (W a, y_q) for q < m, summed on the host in block order
+static int host_wdots(const Level &L, const double *a, const double *Y, int64_t ldY, int m,
+                      double *out, double *partial, hipStream_t s)
+{
+    const int nb = red_grid(L.nL);
+    LAUNCH_V(wdots_kernel, L.nL, s, L.nL, L.W, a, Y, ldY, m, partial);
+    std::vector<double> hp((size_t)nb * kMaxProj);
+    SEM_HIP(hipMemcpyAsync(hp.data(), partial, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < m; ++q) {
+        double acc = 0.0;
+        for (int b = 0; b < nb; ++b) acc += hp[(size_t)b * kMaxProj + q];
+        out[q] = acc;
+    }
+    return SEM_OK;
+}
+
+// projection spaces for slots 0 .. nv-1 with up to L vectors, for h1 A + h2 B
+static int ensure_projection(sem_handle h, int nv, int L, double h1, double h2)
+{
+    Workspace &w = h->ws;
+    const int64_t n = h->lv[0].nL;
+    if (w.proj_L != L) {
+        free_projection(w);
+        w.proj_L = L;
+    }
+    if (w.proj_h1 != h1 || w.proj_h2 != h2) {
+        for (int v = 0; v < kMaxRhs; ++v) w.proj[v].l = 0;
+        w.proj_h1 = h1;
+        w.proj_h2 = h2;
+    }
+    for (int v = 0; v < nv; ++v) {
+        if (!w.proj[v].xt) SEM_HIP(hipMalloc(&w.proj[v].xt, sizeof(double) * n * L));
+        if (!w.proj[v].bt) SEM_HIP(hipMalloc(&w.proj[v].bt, sizeof(double) * n * L));
+    }
+    if (w.proj_nv < nv) {
+        if (w.proj_xb) (void)hipFree(w.proj_xb);
+        if (w.proj_bp) (void)hipFree(w.proj_bp);
+        w.proj_xb = w.proj_bp = nullptr;
+        SEM_HIP(hipMalloc(&w.proj_xb, sizeof(double) * n * nv));
+        SEM_HIP(hipMalloc(&w.proj_bp, sizeof(double) * n * nv));
+        w.proj_nv = nv;
+    }
+    return SEM_OK;
+}
+
+// projected guess of slot v: xb = sum alpha_q xt_q, bp = b - sum alpha_q bt_q
+// with alpha_q = (xt_q, b)_W; returns (b, b)_W and ||bp||_W / ||b||_W
+static int proj_guess(sem_handle h, int v, const double *b, double *bb_out, double *rel_out,
+                      hipStream_t s)
+{
+    Workspace &w = h->ws;
+    const Level &F = h->lv[0];
+    const int64_t n = F.nL;
+    const Workspace::Proj &P = w.proj[v];
+    double *xb = w.proj_xb + v * n, *bp = w.proj_bp + v * n;
+    double bb = 0.0, pp = 0.0;
+    SEM_TRY(host_dot(F, b, b, w.partial, &bb, s));
+    if (P.l > 0) {
+        double al[kMaxProj];
+        SEM_TRY(host_wdots(F, b, P.xt, n, P.l, al, w.partial, s));
+        Coefs ca{}, cb{};
+        for (int q = 0; q < P.l; ++q) {
+            ca.c[q] = al[q];
+            cb.c[q] = -al[q];
+        }
+        LAUNCH_V(lincomb_kernel, n, s, n, (const double *)nullptr, 0.0, (const double *)P.xt, n, P.l,
+                 ca, xb);
+        LAUNCH_V(lincomb_kernel, n, s, n, b, 1.0, (const double *)P.bt, n, P.l, cb, bp);
+    } else {
+        LAUNCH_V(lincomb3_kernel, n, s, n, b, 0.0, (const double *)nullptr, 0.0,
+                 (const double *)nullptr, 0.0, xb);
+        LAUNCH_V(lincomb3_kernel, n, s, n, b, 1.0, (const double *)nullptr, 0.0,
+                 (const double *)nullptr, 0.0, bp);
+    }
+    SEM_TRY(host_dot(F, bp, bp, w.partial, &pp, s));
+    *bb_out = bb;
+    *rel_out = bb > 0.0 ? std::sqrt(std::max(pp, 0.0) / bb) : 0.0;
+    return SEM_OK;
+}
+
+// after the solve of slot v: x holds dx (solution of A dx = bp); grow the
+// space by dx (A-orthogonalised, A-normalised) or restart it from the final
+// x, and complete x = xb + dx
+static int proj_update(sem_handle h, int v, const double *b, double *x, double h1, double h2,
+                       hipStream_t s)
+{
+    Workspace &w = h->ws;
+    const Level &F = h->lv[0];
+    const int64_t n = F.nL;
+    const VSet one = VSet::one();
+    Workspace::Proj &P = w.proj[v];
+    const double *xb = w.proj_xb + v * n, *bp = w.proj_bp + v * n;
+    double *aw = w.w;  // A dx
+    SEM_TRY(launch_ax<double>(F, F.G, F.B, F.D, x, aw, h1, h2, nullptr, nullptr, nullptr, s));
+    SEM_TRY(launch_gs<double>(F, aw, s));
+    LAUNCH_B((mask_kernel<double, double>), n, one, s, n, one, (int64_t)0, F.W, aw);
+    if (P.l < w.proj_L) {
+        double gam[kMaxProj] = {};
+        if (P.l > 0) SEM_TRY(host_wdots(F, aw, P.xt, n, P.l, gam, w.partial, s));
+        Coefs cg{};
+        for (int q = 0; q < P.l; ++q) cg.c[q] = -gam[q];
+        double *xn = P.xt + P.l * n, *bn = P.bt + P.l * n;
+        LAUNCH_V(lincomb_kernel, n, s, n, (const double *)x, 1.0, (const double *)P.xt, n, P.l, cg, xn);
+        LAUNCH_V(lincomb_kernel, n, s, n, (const double *)aw, 1.0, (const double *)P.bt, n, P.l, cg, bn);
+        double nu2 = 0.0, dxw = 0.0;
+        SEM_TRY(host_dot(F, xn, bn, w.partial, &nu2, s));
+        SEM_TRY(host_dot(F, x, aw, w.partial, &dxw, s));
+        if (nu2 > 1e-28 * std::max(dxw, 1e-300)) {
+            const double inv = 1.0 / std::sqrt(nu2);
+            LAUNCH_V(lincomb3_kernel, n, s, n, (const double *)xn, inv, (const double *)nullptr, 0.0,
+                     (const double *)nullptr, 0.0, xn);
+            LAUNCH_V(lincomb3_kernel, n, s, n, (const double *)bn, inv, (const double *)nullptr, 0.0,
+                     (const double *)nullptr, 0.0, bn);
+            P.l += 1;
+        }
+        LAUNCH_V(lincomb3_kernel, n, s, n, (const double *)x, 1.0, xb, 1.0, (const double *)nullptr,
+                 0.0, x);
+    } else {
+        LAUNCH_V(lincomb3_kernel, n, s, n, (const double *)x, 1.0, xb, 1.0, (const double *)nullptr,
+                 0.0, x);
+        // A x = A xb + A dx = (b - bp) + A dx
+        double *x0 = P.xt, *b0 = P.bt;
+        LAUNCH_V(lincomb3_kernel, n, s, n, b, 1.0, bp, -1.0, (const double *)aw, 1.0, b0);
+        double nu2 = 0.0;
+        SEM_TRY(host_dot(F, x, b0, w.partial, &nu2, s));
+        if (nu2 > 0.0) {
+            const double inv = 1.0 / std::sqrt(nu2);
+            LAUNCH_V(lincomb3_kernel, n, s, n, (const double *)x, inv, (const double *)nullptr, 0.0,
+                     (const double *)nullptr, 0.0, x0);
+            LAUNCH_V(lincomb3_kernel, n, s, n, (const double *)b0, inv, (const double *)nullptr, 0.0,
+                     (const double *)nullptr, 0.0, b0);
+            P.l = 1;
+        } else {
+            P.l = 0;
+        }
+    }
+    return SEM_OK;
+}
+
 // nv solves with one operator, in lockstep: vector v's right-hand side and
 // iterate are b + v*ld and x + v*ld; every kernel serves the unconverged ones
 int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, const sem_solve_opts *o,
@@ -954,6 +1166,11 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
     }
     if (pmg && o->k) {
         set_error("sem_pcg_solve: PMG supports constant coefficients only (k = NULL)");
+        return SEM_EINVAL;
+    }
+    const bool proj = o->proj_dim > 0;
+    if (proj && o->k) {
+        set_error("sem_pcg_solve: projected initial guesses need constant coefficients (k = NULL)");
         return SEM_EINVAL;
     }
     SolveCfg cfg{o->h1, o->h2, o->tol, o->coarse_tol, o->maxit, std::max(1, o->check_every),
@@ -997,9 +1214,28 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
     const VSet all = VSet::first(nv);
     const KrylovVecs kv{x, ld, w.r, w.p, w.w, w.sc};
     std::vector<int> coarse_total(nv, 0);
+    // projected initial guesses: solve for the remainder dx (into x) of each
+    // right-hand side, from zero, to the tolerance of the original b
+    std::vector<int> proj_used(nv, 0);
+    std::vector<double> proj_rel(nv, 0.0);
+    BbRef ref{};
+    const double *bs = b;  // right-hand sides the Krylov solve sees
+    int64_t ldbs = ld;
+    if (proj) {
+        SEM_TRY(ensure_projection(h, nv, o->proj_dim, o->h1, o->h2));
+        for (int v = 0; v < nv; ++v) {
+            proj_used[v] = w.proj[v].l;
+            double bb = 0.0;
+            SEM_TRY(proj_guess(h, v, b + v * ld, &bb, &proj_rel[v], s));
+            ref.v[v] = bb;
+        }
+        bs = w.proj_bp;
+        ldbs = n;
+    }
+    const bool zero = proj || o->zero_guess != 0;
     if (!pmg) {
-        SEM_TRY(pcg_start(h, F, all, o->k, o->h1, o->h2, b, ld, kv, o->zero_guess != 0, o->tol,
-                          o->maxit, s));
+        SEM_TRY(pcg_start(h, F, all, o->k, o->h1, o->h2, bs, ldbs, kv, zero, o->tol, o->maxit, ref,
+                          s));
         SEM_TRY(read_scalars(h, false, s));
         VSet act = live_set(w, all);
         int it = 0;
@@ -1012,7 +1248,7 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
     } else {
         // r = b - A x ; z = M r ; p = z ; rz = (z, r)
         const double *Ax = nullptr;
-        if (o->zero_guess) {
+        if (zero) {
             LAUNCH_B(fill_kernel<double>, n, all, s, n, all, ld, x, 0.0);
         } else {
             LAUNCH_B((mask_kernel<double, double>), n, all, s, n, all, ld, F.W, x);
@@ -1022,10 +1258,10 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
             Ax = w.w;
         }
         float *r32 = (float *)w.mg_r[0], *z32 = (float *)w.mg_x[0];  // V-cycle input, output
-        LAUNCH_B(pcg_init_kernel, n, all, s, n, all, ld, b, n, Ax, F.Dinv, F.W, w.r,
+        LAUNCH_B(pcg_init_kernel, n, all, s, n, all, ldbs, bs, n, Ax, F.Dinv, F.W, w.r,
                  (double *)nullptr, r32, w.partial, w.pst, 0);
         LAUNCH_1B(fin_init_kernel, all, s, all, (const double *)w.partial, w.pst,
-                  (int64_t)red_grid(n), w.sc, o->tol, o->maxit);
+                  (int64_t)red_grid(n), w.sc, o->tol, o->maxit, ref);
         SEM_TRY(read_scalars(h, false, s));
         VSet act = live_set(w, all);
         const int nbv = red_grid(n);
@@ -1068,8 +1304,11 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
             cycled = act;
         }
     }
-    const auto t2 = clk::now();
     std::vector<KrylovScalars> hs(w.host_sc, w.host_sc + nv);
+    if (proj)
+        for (int v = 0; v < nv; ++v) SEM_TRY(proj_update(h, v, b + v * ld, x + v * ld, o->h1, o->h2, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    const auto t2 = clk::now();
     std::vector<double> trr(nv, 0.0);
     SEM_TRY(true_residual(h, all, o->k, o->h1, o->h2, b, x, ld, trr.data(), s));
     int rc = SEM_OK;
@@ -1084,6 +1323,8 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
             st[v].ms_setup = std::chrono::duration<double, std::milli>(t1 - t0).count();
             st[v].ms_solve = std::chrono::duration<double, std::milli>(t2 - t1).count();
             st[v].coarse_iters = coarse_total[v];
+            st[v].proj_vectors = proj_used[v];
+            st[v].proj_rel_res = proj_rel[v];
         }
         if (q.status == SEM_EBREAKDOWN) {
             if (rc != SEM_EBREAKDOWN)
@@ -1125,6 +1366,7 @@ int adjoint(sem_handle h, const double *u, const double *g, const sem_solve_opts
     LAUNCH_B((mask_kernel<double, double>), n, one, s, n, one, (int64_t)0, F.W, rhs);
     sem_solve_opts oo = *o;
     oo.zero_guess = 1;
+    oo.proj_dim = 0;  // the forward solves' spaces stay untouched
     if (oo.k != nullptr || h->n_levels < 2) oo.precond = SEM_PRECOND_JACOBI;
     const int rc = pcg_solve(h, 1, rhs, lam, n, &oo, st, s);
     if (rc != SEM_OK && rc != SEM_ENOCONV) return rc;
@@ -1176,12 +1418,27 @@ void sem_solve_opts_default(sem_solve_opts *o)
     o->coarse_tol = 1e-2;
     o->coarse_maxit = 20;
     o->zero_guess = 1;
+    o->proj_dim = 0;
+}
+
+int sem_proj_reset(sem_handle h)
+{
+    if (!h) {
+        set_error("sem_proj_reset: null handle");
+        return SEM_EINVAL;
+    }
+    for (int v = 0; v < kMaxRhs; ++v) h->ws.proj[v].l = 0;
+    return SEM_OK;
 }
 
 static int check_solve_opts(const char *who, const sem_solve_opts *o)
 {
     if (!(o->tol >= 0.0) || o->maxit < 0 || (o->precond != SEM_PRECOND_JACOBI && o->precond != SEM_PRECOND_PMG)) {
         set_error("%s: bad options", who);
+        return SEM_EINVAL;
+    }
+    if (o->proj_dim < 0 || o->proj_dim > kMaxProj) {
+        set_error("%s: proj_dim = %d outside 0..%d", who, o->proj_dim, kMaxProj);
         return SEM_EINVAL;
     }
     if (o->precond == SEM_PRECOND_PMG &&

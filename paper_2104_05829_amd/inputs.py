@@ -177,3 +177,22 @@ def fourier_field(x, y, z, kmax: int = 4, seed: int = 40) -> np.ndarray:
 def sin3(x, y, z) -> np.ndarray:
     """u = sin(pi x) sin(pi y) sin(pi z); -lap u = 3 pi^2 u."""
     return np.sin(math.pi * x) * np.sin(math.pi * y) * np.sin(math.pi * z)
+
+
+def load_sequence(gid: np.ndarray, n_steps: int, seed: int = 60, period: float = 40.0,
+                  eps: float = 1e-3):
+    """Loads f_n for a sequence of solves with slowly varying right-hand sides
+    (a stand-in for successive time steps): fields g0, g1, g2 and a fresh h_n
+    per step from gaussian_per_node (seeds seed, seed+1, seed+2, seed+3+n),
+        f_n = g0 + sin(2 pi n / period) g1 + (n / period)^2 g2 + eps h_n,
+    n = 0 .. n_steps-1 (the eps term keeps the loads out of any fixed
+    low-dimensional span)."""
+    g0, g1, g2 = (gaussian_per_node(gid, seed + i) for i in range(3))
+    out = []
+    for n in range(n_steps):
+        t = n / period
+        f = g0 + np.sin(2.0 * np.pi * t) * g1 + t * t * g2
+        if eps != 0.0:
+            f = f + eps * gaussian_per_node(gid, seed + 3 + n)
+        out.append(f)
+    return out

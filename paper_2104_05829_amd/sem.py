@@ -22,6 +22,7 @@ SEM_OK, SEM_EINVAL, SEM_ENOMEM, SEM_EHIP, SEM_ENOCONV, SEM_EBREAKDOWN, SEM_EMESH
 SEM_F64, SEM_F32 = 0, 1
 SEM_PRECOND_JACOBI, SEM_PRECOND_PMG = 0, 1
 SEM_MAX_RHS = 4
+SEM_MAX_PROJ = 16
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 
@@ -48,13 +49,15 @@ class SemSolveOpts(ctypes.Structure):
                 ("check_every", ctypes.c_int), ("cheb_degree", ctypes.c_int),
                 ("lanczos_steps", ctypes.c_int), ("cheb_lo", ctypes.c_double),
                 ("cheb_hi", ctypes.c_double), ("coarse_tol", ctypes.c_double),
-                ("coarse_maxit", ctypes.c_int), ("zero_guess", ctypes.c_int)]
+                ("coarse_maxit", ctypes.c_int), ("zero_guess", ctypes.c_int),
+                ("proj_dim", ctypes.c_int)]
 
 
 class SemSolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("rel_res", ctypes.c_double),
                 ("true_rel_res", ctypes.c_double), ("ms_solve", ctypes.c_double),
-                ("ms_setup", ctypes.c_double), ("coarse_iters", ctypes.c_int)]
+                ("ms_setup", ctypes.c_double), ("coarse_iters", ctypes.c_int),
+                ("proj_vectors", ctypes.c_int), ("proj_rel_res", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -90,6 +93,7 @@ _SIGS = {
     "sem_pcg_solve_multi": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, ctypes.c_int64,
                                            ctypes.POINTER(SemSolveOpts), _VP, _VP]),
     "sem_solve_opts_default": (None, [ctypes.POINTER(SemSolveOpts)]),
+    "sem_proj_reset": (ctypes.c_int, [_VP]),
     "sem_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(SemSolveOpts),
                                      ctypes.POINTER(SemSolveStats), _VP]),
     "sem_grad_k": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
@@ -398,6 +402,10 @@ class Sem:
         if raise_on_error and rc not in (SEM_OK, SEM_ENOCONV):
             _check(rc, "sem_pcg_solve")
         return x, st.as_dict(), rc
+
+    def proj_reset(self):
+        """Forget the stored solutions of the projected initial guesses."""
+        _check(lib().sem_proj_reset(self._handle()), "sem_proj_reset")
 
     def solve_multi(self, B, X=None, raise_on_error=True, **kw):
         """nrhs solves with one operator in lockstep (rows of B, [nrhs, n_local],

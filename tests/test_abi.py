@@ -111,6 +111,7 @@ def test_host_error_paths():
     assert L.sem_ax_level_multi(None, 0, 0, 3, None, None, 10, 1.0, 0.0, None) == S.SEM_EINVAL
     assert L.sem_gs_level_multi(None, 0, 0, 3, None, 10, None) == S.SEM_EINVAL
     assert L.sem_pcg_solve_multi(None, 3, None, None, 10, ctypes.byref(o), None, None) == S.SEM_EINVAL
+    assert L.sem_proj_reset(None) == S.SEM_EINVAL
     info = S.SemInfo()
     assert L.sem_info(None, 0, ctypes.byref(info)) == S.SEM_EINVAL
 
@@ -120,4 +121,4 @@ def test_default_solver_options():
     assert (o.h1, o.h2, o.tol, o.maxit, o.precond, o.cheb_degree, o.lanczos_steps) == \
         (1.0, 0.0, 1e-8, 1000, S.SEM_PRECOND_JACOBI, 2, 20)
     assert (o.coarse_tol, o.coarse_maxit) == (1e-2, 20)
-    assert (o.cheb_lo, o.cheb_hi, o.zero_guess) == (0.1, 1.1, 1)
+    assert (o.cheb_lo, o.cheb_hi, o.zero_guess, o.proj_dim) == (0.1, 1.1, 1, 0)

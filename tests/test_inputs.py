@@ -64,3 +64,19 @@ def test_interior_zero_and_random_fields():
     x = np.linspace(0, 1, 7)
     v0 = inputs.fourier_field(x, 0 * x + 0.3, 0 * x + 0.6)
     np.testing.assert_allclose(v0[0], v0[-1], atol=1e-12)
+
+
+def test_load_sequence_recipe():
+    """f_n = g0 + sin(2 pi n / T) g1 + (n / T)^2 g2 + eps h_n from seeded
+    per-node Gaussian fields, replicated over the copies of each node."""
+    from paper_2104_05829_amd import inputs as I
+    xi = np.array([-1.0, 0.0, 1.0])
+    m = I.box_mesh(2, 2, 1, xi)
+    seq = I.load_sequence(m.gid, 4, seed=5, period=8.0, eps=0.01)
+    g0, g1, g2 = (I.gaussian_per_node(m.gid, 5 + i) for i in range(3))
+    np.testing.assert_allclose(seq[0], g0 + 0.01 * I.gaussian_per_node(m.gid, 8), rtol=0, atol=1e-15)
+    for n in range(4):
+        t = n / 8.0
+        ref = g0 + np.sin(2 * np.pi * t) * g1 + t * t * g2 + 0.01 * I.gaussian_per_node(m.gid, 8 + n)
+        np.testing.assert_allclose(seq[n], ref, rtol=0, atol=1e-15)
+    assert all(f.shape == (m.n_local,) for f in seq)
