@@ -172,6 +172,27 @@ def bench_pcg(args, torch, sem_mod, inputs):
             if pre == "pmg":
                 lock[pre]["coarse_iters"] = [st["coarse_iters"] for st in sts]
             del X
+    # Schwarz smoothers (CHEBY-ASM / CHEBY-RAS), the three right-hand sides in lockstep
+    schw = {}
+    if "pmg" in pres and not args.no_schwarz:
+        Bt = torch.stack([s.gs(B * torch.tensor(inputs.gaussian_per_node(mesh.gid, seed), device="cuda"))
+                          * (W > 0) for seed in (30, 31, 32)[: args.pcg_rhs]])
+        for smo in ("asm", "ras"):
+            kw = dict(tol=1e-8, h1=1.0, h2=10.0, precond="pmg", smoother=smo, cheb_lo=0.25,
+                      coarse_tol=args.coarse_tol, coarse_maxit=args.coarse_maxit)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.solve_multi(Bt, **kw)  # builds the smoother (host FDM setup) and its lambda_max
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            X, sts, rc = s.solve_multi(Bt, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            schw[smo] = {"ms_total": round(dt * 1e3, 3), "iters": [st["iters"] for st in sts],
+                         "true_rel_res": [float(f"{st['true_rel_res']:.3e}") for st in sts],
+                         "status": rc, "first_call_s": round(t_setup, 3)}
+            del X
     # difference between the two solutions (W-weighted, relative)
     diffs = []
     for a, bb in zip(res.get("pmg", []), res.get("jacobi", [])):
@@ -197,6 +218,11 @@ def bench_pcg(args, torch, sem_mod, inputs):
     for pre, v in lock.items():
         out[pre + "_lockstep"] = v
         v["speedup_vs_independent"] = round(out[pre]["ms_total"] / v["ms_total"], 3)
+    for smo, v in schw.items():
+        v["smoother"] = f"Chebyshev-accelerated {smo.upper()} (FDM local solves), interval [0.25, 1.1] lambda_max"
+        if "pmg_lockstep" in out:
+            v["speedup_vs_cheby_jacobi_lockstep"] = round(out["pmg_lockstep"]["ms_total"] / v["ms_total"], 3)
+        out["pmg_" + smo + "_lockstep"] = v
     if len(pres) == 2:
         out["speedup_pmg_vs_jacobi"] = round(out["jacobi"]["ms_total"] / out["pmg"]["ms_total"], 3)
         out["rel_diff_pmg_vs_jacobi"] = [float(f"{d:.3e}") for d in diffs]
@@ -414,6 +440,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--no-schwarz", action="store_true", help="skip the CHEBY-ASM / CHEBY-RAS solves")
     ap.add_argument("--no-small", action="store_true", help="skip the 4^3 and adjoint records")
     ap.add_argument("--pcg-elems", type=int, default=32)
     ap.add_argument("--pcg-rhs", type=int, default=3)

@@ -66,6 +66,10 @@ enum sem_dtype { SEM_F64 = 0, SEM_F32 = 1 };
 /* Largest projection space (earlier solutions kept per right-hand-side slot). */
 #define SEM_MAX_PROJ 16
 enum sem_precond { SEM_PRECOND_JACOBI = 0, SEM_PRECOND_PMG = 1 };
+/* p-multigrid smoother (Sec. 3.4): Chebyshev-accelerated Jacobi, or
+ * Chebyshev-accelerated overlapping Schwarz with fast-diagonalisation local
+ * solves, combined additively (ASM) or restricted (RAS). */
+enum sem_smoother { SEM_SMOOTH_JACOBI = 0, SEM_SMOOTH_ASM = 1, SEM_SMOOTH_RAS = 2 };
 
 /*
  * Mesh description (host arrays, E*(N+1)^3 entries each, L-vector layout).
@@ -180,6 +184,14 @@ typedef struct {
     int proj_dim;        /* 0: off; L in 1..SEM_MAX_PROJ: initial guess projected onto
                             up to L earlier solutions (see sem_proj_reset); x on entry
                             is then ignored; constant coefficients only (k = NULL) */
+    int smoother;        /* PMG smoother, enum sem_smoother.  Schwarz: subdomain = the
+                            element plus one node layer of its neighbours ((N+3)^3
+                            points), local operator = the separable operator of that box
+                            from the element's mean extents, solved by fast
+                            diagonalisation in FP32; ASM weights the overlapping sum by
+                            1 / (subdomains containing the node); needs N >= 2 on every
+                            smoothed level and a conforming hex mesh; the Chebyshev
+                            interval uses the power-method lambda_max of M^{-1} A */
 } sem_solve_opts;
 
 typedef struct {
@@ -197,7 +209,7 @@ typedef struct {
 /* Fill opts with defaults: h1 = 1, h2 = 0, k = NULL, tol = 1e-8, maxit = 1000,
  * Jacobi, check_every = 8, cheb_degree = 2, lanczos_steps = 20,
  * interval [0.1, 1.1] lambda_max, coarse_tol = 1e-2, coarse_maxit = 20,
- * zero_guess = 1, proj_dim = 0. */
+ * zero_guess = 1, proj_dim = 0, smoother = SEM_SMOOTH_JACOBI. */
 SEM_API void sem_solve_opts_default(sem_solve_opts *opts);
 
 /*
@@ -232,6 +244,37 @@ SEM_API int sem_pcg_solve(sem_handle h, const double *b, double *x, const sem_so
  * this call (all slots).  Device memory: 2 L n_local doubles per slot used.
  */
 SEM_API int sem_proj_reset(sem_handle h);
+
+/*
+ * One application of the overlapping Schwarz smoother of a level (Sec. 3.4;
+ * the construction is described at sem_solve_opts.smoother), for tests and
+ * inspection:  z = M^{-1} r with M^{-1} = weight o QQ^T(sum over subdomains of
+ * the FDM local solutions of r), FP32 device L-vectors of the level (r
+ * replicated, zero on Dirichlet copies; z may not alias r).  smoother =
+ * SEM_SMOOTH_ASM or SEM_SMOOTH_RAS; the level needs N >= 2 and FP32 data
+ * (every level above the coarsest).  Builds the level's Schwarz data on first
+ * use (host work, synchronises `stream` then).
+ */
+SEM_API int sem_smoother_apply(sem_handle h, int level, int smoother, double h1, double h2,
+                               const float *r, float *z, void *stream);
+
+/*
+ * The host part of the Schwarz setup for one level, on host arrays (no
+ * device work; for inspection and tests).  In: order N (>= 2), E elements,
+ * gid and dirichlet per copy (as in sem_mesh; dirichlet may be NULL), len
+ * [E][3] element extents along r, s, t.  Out (each may be NULL; ne = N+3):
+ *   ix     [E][ne^3]        copy gathered at extended point (a, b, c) of each
+ *                           element, a fastest; -1 when absent
+ *   S, lam [E][3][ne][ne], [E][3][ne]  FDM modes (row = point) and eigenvalues
+ *                           per direction r, s, t (padded modes: zero columns, 1)
+ *   cover  [n_local]        extended points (all elements) gathered from each copy
+ *   weight [n_local]        ASM weight: 0 on Dirichlet copies, else 1 / (number
+ *                           of subdomains containing the node)
+ * Returns SEM_EMESH when a face does not conform.
+ */
+SEM_API int sem_schwarz_setup_host(int N, int64_t E, const int64_t *gid, const uint8_t *dirichlet,
+                                   const double *len, int32_t *ix, float *S, float *lam,
+                                   int32_t *cover, float *weight);
 
 /*
  * nrhs independent solves with one operator, advanced in lockstep so that

@@ -19,7 +19,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsem.so")
 ARCH = os.environ.get("SEM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "ax_f64.hip", "ax_f32.hip", "ops.hip", "maps.hip", "solve.hip", "gll.cpp"]
+SOURCES = ["api.hip", "ax_f64.hip", "ax_f32.hip", "ops.hip", "maps.hip", "solve.hip", "schwarz.hip",
+           "gll.cpp"]
 
 CFLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -22,12 +22,42 @@ void set_error(const char *fmt, ...)
 
 static void free_level(Level &L)
 {
+    free_schwarz(L);
     void *ptrs[] = {L.G, L.B, L.G32, L.B32, L.W, L.W32, L.gid, L.dir, L.perm, L.offs,
                     L.chunk_b, L.chunk_e, L.chunk_mask, L.over,
                     L.D, L.D32, L.Jc, L.Jc32, L.Dinv, L.Dinv32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     L = Level{};
+}
+
+// mean extent of each element along r, s, t: the mean distance between the end
+// nodes of the element's node lines in that direction
+__global__ void elem_len_kernel(int64_t E, int nq, const double *__restrict__ x,
+                                const double *__restrict__ y, const double *__restrict__ z,
+                                double *__restrict__ len)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const int N = nq - 1, np = nq * nq * nq;
+    const double *X[3] = {x + e * np, y + e * np, z + e * np};
+    for (int d = 0; d < 3; ++d) {
+        double acc = 0.0;
+        for (int v = 0; v < nq; ++v)
+            for (int u = 0; u < nq; ++u) {
+                int p0, p1;  // line along d through (u, v) of the other two axes
+                if (d == 0) { p0 = (v * nq + u) * nq; p1 = p0 + N; }
+                else if (d == 1) { p0 = v * nq * nq + u; p1 = p0 + N * nq; }
+                else { p0 = v * nq + u; p1 = p0 + N * nq * nq; }
+                double s2 = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    const double dd = X[c][p1] - X[c][p0];
+                    s2 += dd * dd;
+                }
+                acc += sqrt(s2);
+            }
+        len[e * 3 + d] = acc / (nq * nq);
+    }
 }
 
 __global__ void cast_f64_to_f32_kernel(int64_t n, const double *__restrict__ a, float *__restrict__ b)
@@ -120,6 +150,19 @@ static int build_level(Level &L, int N, int64_t E, const double *x, const double
     SEM_HIP(hipMalloc(&L.G, sizeof(double) * 6 * L.nL));
     SEM_HIP(hipMalloc(&L.B, sizeof(double) * L.nL));
     SEM_TRY(launch_geometry(L, x, y, z, L.G, L.B, bad, s));
+    {
+        double *dlen = nullptr;
+        SEM_HIP(hipMalloc(&dlen, sizeof(double) * 3 * E));
+        hipLaunchKernelGGL(elem_len_kernel, dim3((unsigned)((E + 127) / 128)), dim3(128), 0, s, E, L.nq,
+                           x, y, z, dlen);
+        hipError_t e1 = hipGetLastError();
+        L.len.assign(3 * E, 0.0);
+        if (e1 == hipSuccess)
+            e1 = hipMemcpyAsync(L.len.data(), dlen, sizeof(double) * 3 * E, hipMemcpyDeviceToHost, s);
+        if (e1 == hipSuccess) e1 = hipStreamSynchronize(s);
+        (void)hipFree(dlen);
+        SEM_HIP(e1);
+    }
     if (f32) {
         SEM_HIP(hipMalloc(&L.G32, sizeof(float) * 6 * L.nL));
         SEM_HIP(hipMalloc(&L.B32, sizeof(float) * L.nL));

@@ -129,6 +129,20 @@ struct Level {
     double *Dinv = nullptr;
     float *Dinv32 = nullptr;
     double lmax = 0.0;
+    // element extents along r, s, t [E][3] (host), for the Schwarz smoother
+    std::vector<double> len;
+    // overlapping Schwarz smoother (built on first use): extended points
+    // ne = nq + 2 per direction; sz_ix [E][ne^3] copy gathered at each point
+    // (-1 absent); FDM data sz_S [E][3][ne][ne] (row = point, column = mode)
+    // and sz_lam [E][3][ne]; ASM accumulation lists sz_off [nL+1] / sz_src
+    // (indices into the local solutions [E][ne^3], ascending) and weight
+    // sz_w [nL] = mask / (subdomains containing the node)
+    int sz_ne = 0;
+    int32_t *sz_ix = nullptr;
+    float *sz_S = nullptr, *sz_lam = nullptr;
+    int32_t *sz_off = nullptr, *sz_src = nullptr;
+    float *sz_w = nullptr;
+    double sz_lmax = 0.0;  // lambda_max(M^{-1} A) estimate for the current key
 };
 
 struct Workspace {
@@ -161,12 +175,19 @@ struct Workspace {
     int proj_L = 0, proj_nv = 0;
     double proj_h1 = 0.0, proj_h2 = 0.0;
     double *proj_xb = nullptr, *proj_bp = nullptr;
+    // Schwarz smoother: local solutions [nv][E][ne^3] of the largest smoothed
+    // level and the combined sums [nv][nL] per smoothed level
+    float *sz_U = nullptr;
+    int64_t sz_U_len = 0;
+    float *sz_acc[kMaxLevels] = {};
+    int sz_nv = 0;
 };
 
 struct PrecondKey {
     bool valid = false;
     double h1 = 0, h2 = 0;
     int precond = -1;
+    int smoother = 0;
     int cheb_degree = 0, lanczos_steps = 0;
     double lo = 0, hi = 0;
 };
@@ -235,6 +256,17 @@ int launch_restrict_resid(const Level &F, const Level &C, const float *r, const 
 template <typename TI>
 int launch_prolong_add(const Level &F, const Level &C, const TI *in, float *x, const VSet &vs,
                        hipStream_t s);
+
+// overlapping Schwarz smoother of a level (schwarz.hip): build_schwarz fills
+// the sz_* fields; launch_schwarz computes the local FDM solutions of
+// res = r - t (t nullable: res = r) for the batch vs into U [nv][E][ne^3] and
+// their combination acc [nv][nL] before QQ^T (ASM: all points through the
+// accumulation lists; RAS: each copy's own point); the caller applies QQ^T
+// and the weight (sz_w for ASM, W32 for RAS).
+int build_schwarz(Level &L, hipStream_t s);
+void free_schwarz(Level &L);
+int launch_schwarz(const Level &L, bool ras, const float *r, const float *t, float *U, float *acc,
+                   const VSet &vs, double h1, double h2, hipStream_t s);
 
 // setup helpers
 int build_maps(Level &L, const int64_t *gid_dev, const uint8_t *dir_dev, const double *x,

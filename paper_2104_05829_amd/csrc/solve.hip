@@ -392,6 +392,39 @@ __global__ void cheb_fused_kernel(int64_t n, VSet vs, int64_t ld, const float *_
     }
 }
 
+// Chebyshev step with the Schwarz smoother: z = wgt o acc (acc = QQ^T of the
+// combined local solutions), d = c1 d + c2 z, x += d (x = d when `init`)
+__global__ void cheb_w_kernel(int64_t n, VSet vs, int64_t ld, const float *__restrict__ wgt,
+                              const float *__restrict__ acc, float *__restrict__ d,
+                              float *__restrict__ x, float c1, float c2, int init)
+{
+    const int64_t v = vsel(vs);
+    acc += v * ld;
+    d += v * ld;
+    x += v * ld;
+    GRID_LOOP(i, n) {
+        const float di = (init ? 0.0f : c1 * d[i]) + c2 * wgt[i] * acc[i];
+        d[i] = di;
+        x[i] = init ? di : x[i] + di;
+    }
+}
+
+// partial (W a b) sums of FP32 vectors in FP64
+__global__ void dot32_kernel(int64_t n, const double *__restrict__ W, const float *__restrict__ a,
+                             const float *__restrict__ b, double *__restrict__ partial)
+{
+    double s[1] = {0.0};
+    GRID_LOOP(i, n) s[0] += W[i] * (double)a[i] * (double)b[i];
+    block_sum_store<1>(s, partial);
+}
+
+// y = alpha (w o x)   (w nullable: y = alpha x)
+__global__ void wscale32_kernel(int64_t n, const float *__restrict__ w, const float *__restrict__ x,
+                                float alpha, float *__restrict__ y)
+{
+    GRID_LOOP(i, n) y[i] = alpha * (w ? w[i] * x[i] : x[i]);
+}
+
 // s = W (r - t) for assembled t
 __global__ void wresid_fused_kernel(int64_t n, VSet vs, int64_t ld, const float *__restrict__ W,
                                     const float *__restrict__ r, const float *__restrict__ t,
@@ -589,6 +622,9 @@ void free_workspace(sem_handle h)
     Workspace &w = h->ws;
     free_vectors(w);
     free_projection(w);
+    if (w.sz_U) (void)hipFree(w.sz_U);
+    for (int l = 0; l < kMaxLevels; ++l)
+        if (w.sz_acc[l]) (void)hipFree(w.sz_acc[l]);
     void *ptrs[] = {w.aux, w.partial, w.partial_ax, w.sc, w.sc_c};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -778,37 +814,144 @@ static int apply_f32(const Level &L, const VSet &vs, const float *x, float *t, d
 
 // Chebyshev-accelerated Jacobi (Saad, Iterative Methods, Alg. 12.1, applied to
 // Dinv A x = Dinv r) with `deg` updates; x == 0 on entry when `zero`.
-static int chebyshev(const Level &L, int l, sem_handle h, const VSet &vs, const float *r, float *x,
-                     bool zero, double lmin, double lmax, int deg, double h1, double h2,
-                     hipStream_t s)
+// one smoothing correction of the batch: with Jacobi, d = c1 d + c2 Dinv (r - t)
+// fused; with Schwarz, the local FDM solutions of r - t combined, QQ^T and
+// weighted, then d = c1 d + c2 z.  t null: x = 0 (res = r).
+static int smooth_step(const Level &L, int l, sem_handle h, const VSet &vs, int smoother,
+                       const float *r, const float *t, float *d, float *x, float c1, float c2,
+                       int init, double h1, double h2, hipStream_t s)
+{
+    const int64_t n = L.nL;
+    if (smoother == SEM_SMOOTH_JACOBI) {
+        LAUNCH_B(cheb_fused_kernel, n, vs, s, n, vs, n, r, t, L.Dinv32, d, x, c1, c2, init);
+        return SEM_OK;
+    }
+    Workspace &w = h->ws;
+    const bool ras = smoother == SEM_SMOOTH_RAS;
+    float *acc = w.sz_acc[l];
+    SEM_TRY(launch_schwarz(L, ras, r, t, w.sz_U, acc, vs, h1, h2, s));
+    SEM_TRY(launch_gs_multi<float>(L, acc, n, vs, s, nullptr, 0));
+    LAUNCH_B(cheb_w_kernel, n, vs, s, n, vs, n, (const float *)(ras ? L.W32 : L.sz_w),
+             (const float *)acc, d, x, c1, c2, init);
+    return SEM_OK;
+}
+
+// Chebyshev acceleration (Saad, Iterative Methods, Alg. 12.1) of the smoother
+// x <- x + M^{-1}(r - A x), M = Jacobi or Schwarz, with `deg` updates; x == 0
+// on entry when `zero`.
+static int chebyshev(const Level &L, int l, sem_handle h, const VSet &vs, int smoother,
+                     const float *r, float *x, bool zero, double lmin, double lmax, int deg,
+                     double h1, double h2, hipStream_t s)
 {
     Workspace &w = h->ws;
     float *t = (float *)w.mg_t[l], *d = (float *)w.mg_d[l];
-    const int64_t n = L.nL;
     const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
     const double sigma = theta / delta;
     double rho_prev = 1.0 / sigma;
     if (zero) {
-        LAUNCH_B(cheb_fused_kernel, n, vs, s, n, vs, n, r, (const float *)nullptr, L.Dinv32, d, x,
-                 0.0f, (float)(1.0 / theta), 1);
+        SEM_TRY(smooth_step(L, l, h, vs, smoother, r, nullptr, d, x, 0.0f, (float)(1.0 / theta), 1, h1,
+                            h2, s));
     } else {
         SEM_TRY(apply_f32(L, vs, x, t, h1, h2, s));
-        LAUNCH_B(cheb_fused_kernel, n, vs, s, n, vs, n, r, (const float *)t, L.Dinv32, d, x, 0.0f,
-                 (float)(1.0 / theta), 0);
+        SEM_TRY(smooth_step(L, l, h, vs, smoother, r, t, d, x, 0.0f, (float)(1.0 / theta), 0, h1, h2,
+                            s));
     }
     for (int k = 1; k < deg; ++k) {
         const double rho = 1.0 / (2.0 * sigma - rho_prev);
         SEM_TRY(apply_f32(L, vs, x, t, h1, h2, s));
-        LAUNCH_B(cheb_fused_kernel, n, vs, s, n, vs, n, r, (const float *)t, L.Dinv32, d, x,
-                 (float)(rho * rho_prev), (float)(2.0 * rho / delta), 0);
+        SEM_TRY(smooth_step(L, l, h, vs, smoother, r, t, d, x, (float)(rho * rho_prev),
+                            (float)(2.0 * rho / delta), 0, h1, h2, s));
         rho_prev = rho;
     }
+    return SEM_OK;
+}
+
+// Schwarz workspace for batches of nv vectors
+static int ensure_schwarz_ws(sem_handle h, int nv)
+{
+    Workspace &w = h->ws;
+    const int ns = h->n_levels - 1;  // smoothed levels
+    int64_t ulen = 0;
+    for (int l = 0; l < ns; ++l) {
+        const int64_t ne = h->lv[l].nq + 2;
+        ulen = std::max(ulen, h->lv[l].E * ne * ne * ne);
+    }
+    bool have = w.sz_U && w.sz_nv >= nv && w.sz_U_len >= ulen;
+    for (int l = 0; l < ns; ++l) have = have && w.sz_acc[l] != nullptr;
+    if (have) return SEM_OK;
+    if (w.sz_U) (void)hipFree(w.sz_U);
+    w.sz_U = nullptr;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        if (w.sz_acc[l]) (void)hipFree(w.sz_acc[l]);
+        w.sz_acc[l] = nullptr;
+    }
+    const int nvn = std::max(nv, w.sz_nv);
+    ulen = std::max(ulen, w.sz_U_len);
+    SEM_HIP(hipMalloc(&w.sz_U, sizeof(float) * ulen * nvn));
+    for (int l = 0; l < ns; ++l) SEM_HIP(hipMalloc(&w.sz_acc[l], sizeof(float) * h->lv[l].nL * nvn));
+    w.sz_U_len = ulen;
+    w.sz_nv = nvn;
+    return SEM_OK;
+}
+
+// host (W a, b) of FP32 vectors
+static int host_dot32(const Level &L, const float *a, const float *b, double *partial, double *out,
+                      hipStream_t s)
+{
+    const int nb = red_grid(L.nL);
+    LAUNCH_V(dot32_kernel, L.nL, s, L.nL, L.W, a, b, partial);
+    std::vector<double> hp(nb);
+    SEM_HIP(hipMemcpyAsync(hp.data(), partial, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    *out = host_sum_partials(hp);
+    return SEM_OK;
+}
+
+// lambda_max(M^{-1} A) of smoothed level l for the Schwarz smoother by the
+// power method (W-norm ratio) in the smoother's FP32 arithmetic, started from
+// the SplitMix64 values of the global pointers
+static int schwarz_lmax(sem_handle h, int l, int smoother, double h1, double h2, int steps,
+                        double *lmax, hipStream_t s)
+{
+    Level &L = h->lv[l];
+    Workspace &w = h->ws;
+    const int64_t n = L.nL;
+    const VSet one = VSet::one();
+    const bool ras = smoother == SEM_SMOOTH_RAS;
+    float *v = (float *)w.mg_x[l], *t = (float *)w.mg_t[l], *z = (float *)w.mg_d[l];
+    float *acc = w.sz_acc[l];
+    LAUNCH_V(splitmix_kernel, n, s, n, L.gid, L.W, h->lanczos_seed, w.r);
+    LAUNCH_B((convert_kernel<double, float>), n, one, s, n, one, (int64_t)0, (const double *)w.r,
+             (int64_t)0, v);
+    double nv2 = 0.0;
+    SEM_TRY(host_dot32(L, v, v, w.partial, &nv2, s));
+    if (!(nv2 > 0.0)) {
+        *lmax = 1.0;
+        return SEM_OK;
+    }
+    LAUNCH_V(wscale32_kernel, n, s, n, (const float *)nullptr, (const float *)v,
+             (float)(1.0 / std::sqrt(nv2)), v);
+    double lam = 1.0;
+    for (int it = 0; it < steps; ++it) {
+        SEM_TRY(apply_f32(L, one, v, t, h1, h2, s));
+        SEM_TRY(launch_schwarz(L, ras, t, nullptr, w.sz_U, acc, one, h1, h2, s));
+        SEM_TRY(launch_gs_multi<float>(L, acc, n, one, s, nullptr, 0));
+        LAUNCH_V(wscale32_kernel, n, s, n, (const float *)(ras ? L.W32 : L.sz_w), (const float *)acc,
+                 1.0f, z);
+        double z2 = 0.0;
+        SEM_TRY(host_dot32(L, z, z, w.partial, &z2, s));
+        lam = std::sqrt(std::max(z2, 0.0));
+        if (!(lam > 0.0)) break;
+        LAUNCH_V(wscale32_kernel, n, s, n, (const float *)nullptr, (const float *)z, (float)(1.0 / lam), v);
+    }
+    *lmax = lam > 0.0 ? lam : 1.0;
     return SEM_OK;
 }
 
 struct SolveCfg {
     double h1, h2, tol, coarse_tol;
     int maxit, check_every, deg, coarse_maxit;
+    int smoother;
 };
 
 // Vector arrays of one Krylov solve on a level: x may be the caller's array
@@ -890,11 +1033,11 @@ static int vcycle(sem_handle h, int l, const VSet &vs, const SolveCfg &cfg, hipS
     }
     float *r = (float *)w.mg_r[l], *x = (float *)w.mg_x[l], *t = (float *)w.mg_t[l],
           *sres = (float *)w.mg_s[l];
-    const double lmax = L.lmax;
+    const double lmax = cfg.smoother == SEM_SMOOTH_JACOBI ? L.lmax : L.sz_lmax;
     const double lmin_f = h->key.lo, lmax_f = h->key.hi;
     // pre-smoothing from x = 0
-    SEM_TRY(chebyshev(L, l, h, vs, r, x, true, lmin_f * lmax, lmax_f * lmax, cfg.deg, cfg.h1,
-                      cfg.h2, s));
+    SEM_TRY(chebyshev(L, l, h, vs, cfg.smoother, r, x, true, lmin_f * lmax, lmax_f * lmax, cfg.deg,
+                      cfg.h1, cfg.h2, s));
     // restricted residual s = W (r - A x), coarse-grid correction x += J e_c
     SEM_TRY(apply_f32(L, vs, x, t, cfg.h1, cfg.h2, s));
     const Level &C = h->lv[l + 1];
@@ -956,8 +1099,8 @@ static int vcycle(sem_handle h, int l, const VSet &vs, const SolveCfg &cfg, hipS
         LAUNCH_B(add_kernel<float>, n, vs, s, n, vs, n, (const float *)sres, x);
     }
     // post-smoothing
-    SEM_TRY(chebyshev(L, l, h, vs, r, x, false, lmin_f * lmax, lmax_f * lmax, cfg.deg, cfg.h1,
-                      cfg.h2, s));
+    SEM_TRY(chebyshev(L, l, h, vs, cfg.smoother, r, x, false, lmin_f * lmax, lmax_f * lmax, cfg.deg,
+                      cfg.h1, cfg.h2, s));
     return SEM_OK;
 }
 
@@ -1174,7 +1317,8 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
         return SEM_EINVAL;
     }
     SolveCfg cfg{o->h1, o->h2, o->tol, o->coarse_tol, o->maxit, std::max(1, o->check_every),
-                 std::max(1, o->cheb_degree), std::max(1, o->coarse_maxit)};
+                 std::max(1, o->cheb_degree), std::max(1, o->coarse_maxit),
+                 pmg ? o->smoother : SEM_SMOOTH_JACOBI};
     const auto t0 = clk::now();
     SEM_TRY(ensure_workspace(h, pmg, nv));
     Workspace &w = h->ws;
@@ -1186,6 +1330,7 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
     key.h1 = o->h1;
     key.h2 = o->h2;
     key.precond = o->precond;
+    key.smoother = cfg.smoother;
     key.cheb_degree = pmg ? cfg.deg : 0;
     key.lanczos_steps = pmg ? o->lanczos_steps : 0;
     key.lo = pmg ? o->cheb_lo : 0;
@@ -1193,15 +1338,25 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
     const PrecondKey &old = h->key;
     const bool same = !o->k && old.valid && old.h1 == key.h1 && old.h2 == key.h2 &&
                       (old.precond == key.precond || !pmg) && old.lanczos_steps >= key.lanczos_steps &&
-                      (!pmg || (old.precond == SEM_PRECOND_PMG && old.lanczos_steps == key.lanczos_steps));
+                      (!pmg || (old.precond == SEM_PRECOND_PMG && old.lanczos_steps == key.lanczos_steps &&
+                                old.smoother == key.smoother));
+    if (cfg.smoother != SEM_SMOOTH_JACOBI) {
+        for (int l = 0; l + 1 < h->n_levels; ++l) SEM_TRY(build_schwarz(h->lv[l], s));
+        SEM_TRY(ensure_schwarz_ws(h, nv));
+    }
     if (!same) {
         h->key.valid = false;
         SEM_TRY(compute_dinv(h, 0, o->k, o->h1, o->h2, pmg, s));
         if (pmg) {
             for (int l = 1; l < h->n_levels; ++l)
                 SEM_TRY(compute_dinv(h, l, nullptr, o->h1, o->h2, l < h->n_levels - 1, s));
-            for (int l = 0; l + 1 < h->n_levels; ++l)
-                SEM_TRY(lanczos_lmax(h, l, o->h1, o->h2, std::max(2, o->lanczos_steps), &h->lv[l].lmax, s));
+            for (int l = 0; l + 1 < h->n_levels; ++l) {
+                if (cfg.smoother == SEM_SMOOTH_JACOBI)
+                    SEM_TRY(lanczos_lmax(h, l, o->h1, o->h2, std::max(2, o->lanczos_steps), &h->lv[l].lmax, s));
+                else
+                    SEM_TRY(schwarz_lmax(h, l, cfg.smoother, o->h1, o->h2, std::max(2, o->lanczos_steps),
+                                         &h->lv[l].sz_lmax, s));
+            }
         }
         if (!o->k) h->key = key;
     }
@@ -1419,6 +1574,53 @@ void sem_solve_opts_default(sem_solve_opts *o)
     o->coarse_maxit = 20;
     o->zero_guess = 1;
     o->proj_dim = 0;
+    o->smoother = SEM_SMOOTH_JACOBI;
+}
+
+int sem_smoother_apply(sem_handle h, int level, int smoother, double h1, double h2, const float *r,
+                       float *z, void *stream)
+{
+    if (!h || !r || !z) {
+        set_error("sem_smoother_apply: null argument");
+        return SEM_EINVAL;
+    }
+    if (level < 0 || level >= h->n_levels) {
+        set_error("sem_smoother_apply: level %d not in handle (%d levels)", level, h->n_levels);
+        return SEM_EINVAL;
+    }
+    if (smoother != SEM_SMOOTH_ASM && smoother != SEM_SMOOTH_RAS) {
+        set_error("sem_smoother_apply: smoother must be SEM_SMOOTH_ASM or SEM_SMOOTH_RAS");
+        return SEM_EINVAL;
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    Level &L = h->lv[level];
+    if (!L.W32) {
+        set_error("sem_smoother_apply: level %d has no FP32 data", level);
+        return SEM_EINVAL;
+    }
+    SEM_TRY(build_schwarz(L, s));
+    SEM_TRY(ensure_workspace(h, false, 1));
+    // this level's buffers (the handle's smoothed levels may not include it)
+    Workspace &w = h->ws;
+    const int64_t ne = L.nq + 2, ulen = L.E * ne * ne * ne;
+    if (!w.sz_U || w.sz_U_len < ulen) {
+        // one vector's worth for this level; the solver's batch buffers are
+        // sized again by ensure_schwarz_ws when a solve needs them
+        if (w.sz_U) (void)hipFree(w.sz_U);
+        w.sz_U = nullptr;
+        const int nvn = std::max(1, w.sz_nv);
+        const int64_t len = std::max<int64_t>(ulen, w.sz_U_len);
+        SEM_HIP(hipMalloc(&w.sz_U, sizeof(float) * len * nvn));
+        w.sz_U_len = len;
+        w.sz_nv = nvn;
+    }
+    const VSet one = VSet::one();
+    const bool ras = smoother == SEM_SMOOTH_RAS;
+    SEM_TRY(launch_schwarz(L, ras, r, nullptr, w.sz_U, z, one, h1, h2, s));
+    SEM_TRY(launch_gs_multi<float>(L, z, L.nL, one, s, nullptr, 0));
+    LAUNCH_V(wscale32_kernel, L.nL, s, L.nL, (const float *)(ras ? L.W32 : L.sz_w), (const float *)z,
+             1.0f, z);
+    return SEM_OK;
 }
 
 int sem_proj_reset(sem_handle h)
@@ -1435,6 +1637,10 @@ static int check_solve_opts(const char *who, const sem_solve_opts *o)
 {
     if (!(o->tol >= 0.0) || o->maxit < 0 || (o->precond != SEM_PRECOND_JACOBI && o->precond != SEM_PRECOND_PMG)) {
         set_error("%s: bad options", who);
+        return SEM_EINVAL;
+    }
+    if (o->smoother != SEM_SMOOTH_JACOBI && o->smoother != SEM_SMOOTH_ASM && o->smoother != SEM_SMOOTH_RAS) {
+        set_error("%s: bad smoother %d", who, o->smoother);
         return SEM_EINVAL;
     }
     if (o->proj_dim < 0 || o->proj_dim > kMaxProj) {

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libsem.so")
 SEM_OK, SEM_EINVAL, SEM_ENOMEM, SEM_EHIP, SEM_ENOCONV, SEM_EBREAKDOWN, SEM_EMESH = 0, -1, -2, -3, -4, -5, -6
 SEM_F64, SEM_F32 = 0, 1
 SEM_PRECOND_JACOBI, SEM_PRECOND_PMG = 0, 1
+SEM_SMOOTH_JACOBI, SEM_SMOOTH_ASM, SEM_SMOOTH_RAS = 0, 1, 2
 SEM_MAX_RHS = 4
 SEM_MAX_PROJ = 16
 
@@ -50,7 +51,7 @@ class SemSolveOpts(ctypes.Structure):
                 ("lanczos_steps", ctypes.c_int), ("cheb_lo", ctypes.c_double),
                 ("cheb_hi", ctypes.c_double), ("coarse_tol", ctypes.c_double),
                 ("coarse_maxit", ctypes.c_int), ("zero_guess", ctypes.c_int),
-                ("proj_dim", ctypes.c_int)]
+                ("proj_dim", ctypes.c_int), ("smoother", ctypes.c_int)]
 
 
 class SemSolveStats(ctypes.Structure):
@@ -94,6 +95,10 @@ _SIGS = {
                                            ctypes.POINTER(SemSolveOpts), _VP, _VP]),
     "sem_solve_opts_default": (None, [ctypes.POINTER(SemSolveOpts)]),
     "sem_proj_reset": (ctypes.c_int, [_VP]),
+    "sem_schwarz_setup_host": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP,
+                                              _VP, _VP, _VP]),
+    "sem_smoother_apply": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_double, _VP, _VP, _VP]),
     "sem_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(SemSolveOpts),
                                      ctypes.POINTER(SemSolveStats), _VP]),
     "sem_grad_k": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
@@ -141,6 +146,26 @@ def gll(N: int):
     D = np.zeros((N + 1) * (N + 1))
     _check(lib().sem_gll(N, xi.ctypes.data, rho.ctypes.data, D.ctypes.data), "sem_gll")
     return xi, rho, D.reshape(N + 1, N + 1)
+
+
+def schwarz_setup_host(N, gid, dirichlet, lengths):
+    """Host part of the library's Schwarz setup (numpy in, numpy out):
+    (ix [E, ne, ne, ne], S [E, 3, ne, ne], lam [E, 3, ne], cover, weight)."""
+    gid = np.ascontiguousarray(gid, dtype=np.int64).reshape(-1)
+    nq = N + 1
+    E = gid.size // nq ** 3
+    ne = N + 3
+    dirichlet = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8).reshape(-1)
+    lengths = np.ascontiguousarray(lengths, dtype=np.float64).reshape(E, 3)
+    ix = np.zeros((E, ne, ne, ne), dtype=np.int32)
+    S = np.zeros((E, 3, ne, ne), dtype=np.float32)
+    lam = np.zeros((E, 3, ne), dtype=np.float32)
+    cover = np.zeros(gid.size, dtype=np.int32)
+    weight = np.zeros(gid.size, dtype=np.float32)
+    ptr = lambda a: None if a is None else ctypes.c_void_p(a.ctypes.data)  # noqa: E731
+    _check(lib().sem_schwarz_setup_host(N, E, ptr(gid), ptr(dirichlet), ptr(lengths), ptr(ix), ptr(S),
+                                        ptr(lam), ptr(cover), ptr(weight)), "sem_schwarz_setup_host")
+    return ix, S, lam, cover, weight
 
 
 def box_mesh(ex, ey, ez, N, **kw) -> inputs.BoxMesh:
@@ -350,6 +375,10 @@ class Sem:
         pre = kw.pop("precond", None)
         if pre is not None:
             o.precond = {"jacobi": SEM_PRECOND_JACOBI, "pmg": SEM_PRECOND_PMG}.get(pre, pre)
+        smo = kw.pop("smoother", None)
+        if smo is not None:
+            o.smoother = {"jacobi": SEM_SMOOTH_JACOBI, "asm": SEM_SMOOTH_ASM,
+                          "ras": SEM_SMOOTH_RAS}.get(smo, smo)
         for name, val in kw.items():
             if not hasattr(o, name):
                 raise TypeError(f"unknown solver option {name}")
@@ -402,6 +431,18 @@ class Sem:
         if raise_on_error and rc not in (SEM_OK, SEM_ENOCONV):
             _check(rc, "sem_pcg_solve")
         return x, st.as_dict(), rc
+
+    def smoother_apply(self, level, r, z=None, smoother="asm", h1=1.0, h2=0.0):
+        """z = M^{-1} r for the level's Schwarz smoother (FP32 L-vectors)."""
+        torch = _torch()
+        n = self.info(level)["n_local"]
+        if z is None:
+            z = torch.empty_like(r)
+        code = {"asm": SEM_SMOOTH_ASM, "ras": SEM_SMOOTH_RAS}.get(smoother, smoother)
+        _check(lib().sem_smoother_apply(self._handle(), level, code, float(h1), float(h2),
+                                        _dev_ptr(r, torch.float32, n, "r"), _dev_ptr(z, torch.float32, n, "z"),
+                                        _stream()), "sem_smoother_apply")
+        return z
 
     def proj_reset(self):
         """Forget the stored solutions of the projected initial guesses."""
