@@ -128,14 +128,15 @@ struct FaceLink {
 
 void free_schwarz(Level &L)
 {
-    void *ptrs[] = {L.sz_ix, L.sz_S, L.sz_lam, L.sz_off, L.sz_src, L.sz_w};
+    void *ptrs[] = {L.sz_ix, L.sz_S, L.sz_lam, L.sz_rc, L.sz_off, L.sz_src, L.sz_w};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     L.sz_ix = nullptr;
     L.sz_S = L.sz_lam = nullptr;
-    L.sz_off = L.sz_src = nullptr;
+    L.sz_rc = L.sz_off = L.sz_src = nullptr;
     L.sz_w = nullptr;
-    L.sz_ne = 0;
+    L.sz_ne = L.sz_next = 0;
+    L.sz_nrc = 0;
 }
 
 // Host setup of one level: gather map ix [E][ne^3], FDM data S [E][3][ne][ne]
@@ -343,154 +344,231 @@ int build_schwarz(Level &L, hipStream_t s)
     SEM_HIP(hipStreamSynchronize(s));
     SchwarzHost H;
     SEM_TRY(schwarz_host(L.N, L.E, gid.data(), dir.data(), L.len.data(), H));
+    // compact extension map and the lists of copies receiving extension values
+    const int ne = L.N + 3, nq = L.nq;
+    const int next = ne * ne * ne - nq * nq * nq;
+    const int64_t E = L.E, ne3 = (int64_t)ne * ne * ne;
+    std::vector<int32_t> hx((size_t)E * next, -1);
+    std::vector<std::pair<int32_t, int32_t>> contrib;  // (copy, extension entry)
+    for (int64_t e = 0; e < E; ++e)
+        for (int c = 0; c < ne; ++c)
+            for (int b = 0; b < ne; ++b)
+                for (int a = 0; a < ne; ++a) {
+                    const bool inner = a > 0 && a < ne - 1 && b > 0 && b < ne - 1 && c > 0 && c < ne - 1;
+                    if (inner) continue;
+                    const int32_t q = H.ix[(size_t)e * ne3 + ((int64_t)c * ne + b) * ne + a];
+                    const int64_t slot = e * next + schwarz_ext_slot(ne, a, b, c);
+                    hx[slot] = q;
+                    if (q >= 0) contrib.emplace_back(q, (int32_t)slot);
+                }
+    std::sort(contrib.begin(), contrib.end());
+    std::vector<int32_t> rc, off, src;
+    for (size_t i = 0; i < contrib.size();) {
+        size_t j = i;
+        rc.push_back(contrib[i].first);
+        off.push_back((int32_t)src.size());
+        while (j < contrib.size() && contrib[j].first == contrib[i].first) src.push_back(contrib[j++].second);
+        i = j;
+    }
+    off.push_back((int32_t)src.size());
     auto up = [&](void **dst, const void *src_, size_t bytes) -> int {
         SEM_HIP(hipMalloc(dst, bytes > 0 ? bytes : 4));
         if (bytes) SEM_HIP(hipMemcpyAsync(*dst, src_, bytes, hipMemcpyHostToDevice, s));
         return SEM_OK;
     };
-    SEM_TRY(up((void **)&L.sz_ix, H.ix.data(), sizeof(int32_t) * H.ix.size()));
+    SEM_TRY(up((void **)&L.sz_ix, hx.data(), sizeof(int32_t) * hx.size()));
     SEM_TRY(up((void **)&L.sz_S, H.S.data(), sizeof(float) * H.S.size()));
     SEM_TRY(up((void **)&L.sz_lam, H.lam.data(), sizeof(float) * H.lam.size()));
-    SEM_TRY(up((void **)&L.sz_off, H.off.data(), sizeof(int32_t) * H.off.size()));
-    SEM_TRY(up((void **)&L.sz_src, H.src.data(), sizeof(int32_t) * H.src.size()));
+    SEM_TRY(up((void **)&L.sz_rc, rc.data(), sizeof(int32_t) * rc.size()));
+    SEM_TRY(up((void **)&L.sz_off, off.data(), sizeof(int32_t) * off.size()));
+    SEM_TRY(up((void **)&L.sz_src, src.data(), sizeof(int32_t) * src.size()));
     SEM_TRY(up((void **)&L.sz_w, H.w.data(), sizeof(float) * H.w.size()));
     SEM_HIP(hipStreamSynchronize(s));
-    L.sz_ne = L.N + 3;
+    L.sz_ne = ne;
+    L.sz_next = next;
+    L.sz_nrc = (int64_t)rc.size();
     return SEM_OK;
 }
 
 // ------------------------------------------------------------------ kernels
-// Local FDM solve of one element per workgroup: thread (a, b) of the ne x ne
-// point columns keeps the c-line in registers; the c contraction runs in
-// registers, the b and a contractions through LDS planes.  FP32.
+// Local FDM solves, EPB elements per 256-thread workgroup: thread (a, b) of an
+// element's ne x ne point columns keeps the c-line in registers; the
+// element's S matrices and eigenvalues along c sit in LDS; the b and a
+// contractions run through two LDS buffers.  Own points are read directly and
+// written to acc; extension points are gathered through the compact map and
+// (ASM) written to U.  FP32.
 template <int NE>
-__global__ void __launch_bounds__(((NE * NE + 63) / 64) * 64)
+struct FdmShape {
+    static constexpr int NQ = NE - 2, NE2 = NE * NE, THREADS = 256;
+    static constexpr int EPB = THREADS / NE2;
+    static constexpr int NEXT = NE * NE * NE - NQ * NQ * NQ;
+    static constexpr int LDP = NE + 1;
+};
+
+template <int NE, bool EXT_OUT>
+__global__ void __launch_bounds__(256)
 fdm_kernel(int64_t E, const int32_t *__restrict__ ix, const float *__restrict__ Sg,
            const float *__restrict__ lamg, const float *__restrict__ r, const float *__restrict__ t,
-           int64_t ld, float *__restrict__ U, float h1, float h2, VSet vs)
+           int64_t ld, float *__restrict__ acc, float *__restrict__ U, float h1, float h2, VSet vs)
 {
-    constexpr int NE2 = NE * NE, NE3 = NE * NE * NE, LDP = NE + 1;
-    __shared__ float sS[3][NE][NE];
-    __shared__ float slam[3][NE];
-    __shared__ float sa[NE][NE][LDP];  // [c][b][a]
-    __shared__ float sb[NE][NE][LDP];
+    using F = FdmShape<NE>;
+    constexpr int NQ = F::NQ, NE2 = F::NE2, EPB = F::EPB, NEXT = F::NEXT, LDP = F::LDP;
+    constexpr int NP = NQ * NQ * NQ;
+    __shared__ float sS[EPB][3][NE][NE];  // Sx, Sy, Sz of each element
+    __shared__ float slz[EPB][NE];
+    __shared__ float sa[EPB][NE][NE][LDP];  // [c][b][a]
+    __shared__ float sb[EPB][NE][NE][LDP];
     const int64_t v = vs.at(blockIdx.y);
     r += v * ld;
     if (t) t += v * ld;
-    U += v * E * NE3;
+    acc += v * ld;
+    if (EXT_OUT) U += v * E * NEXT;
     const int tid = threadIdx.x;
-    const bool act = tid < NE2;
-    const int a = tid % NE, b = tid / NE;
-    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
-        __syncthreads();  // LDS of the previous element consumed
-        for (int q = tid; q < 3 * NE2; q += blockDim.x) (&sS[0][0][0])[q] = Sg[e * 3 * NE2 + q];
-        for (int q = tid; q < 3 * NE; q += blockDim.x) (&slam[0][0])[q] = lamg[e * 3 * NE + q];
+    const int el = tid / NE2, ij = tid - el * NE2;
+    const int a = ij % NE, b = ij / NE;
+    const bool lane = el < EPB;
+    const bool acol = a == 0 || a == NE - 1 || b == 0 || b == NE - 1;  // border column
+    // extension slots of this column: ebase + c (border column), or ebase and
+    // ebase + 1 for c = 0 and c = ne-1 (inner column)
+    const int ebase = schwarz_ext_slot(NE, a, b, 0);
+    const int64_t groups = (E + EPB - 1) / EPB;
+    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int64_t e = g * EPB + el;
+        const bool act = lane && e < E;
+        __syncthreads();  // LDS of the previous group consumed
         float vv[NE], w[NE];
+        float lxa = 1.0f, lyb = 1.0f;
         if (act) {
+            const float *Se = Sg + e * 3 * NE2;
 #pragma unroll
-            for (int c = 0; c < NE; ++c) {
-                const int32_t q = ix[e * NE3 + (c * NE + b) * NE + a];
-                vv[c] = q >= 0 ? (t ? r[q] - t[q] : r[q]) : 0.0f;
+            for (int d = 0; d < 3; ++d) (&sS[el][d][0][0])[ij] = Se[d * NE2 + ij];
+            if (ij < NE) slz[el][ij] = lamg[e * 3 * NE + 2 * NE + ij];
+            lxa = lamg[e * 3 * NE + a];
+            lyb = lamg[e * 3 * NE + NE + b];
+            const int32_t *ixe = ix + e * NEXT;
+            auto gather = [&](int slot) {
+                const int32_t q = ixe[slot];
+                return q >= 0 ? (t ? r[q] - t[q] : r[q]) : 0.0f;
+            };
+            if (acol) {
+#pragma unroll
+                for (int c = 0; c < NE; ++c) vv[c] = gather(ebase + c);
+            } else {
+                const float *re = r + e * NP + (b - 1) * NQ + (a - 1);
+                const float *te = t ? t + e * NP + (b - 1) * NQ + (a - 1) : nullptr;
+                vv[0] = gather(ebase);
+#pragma unroll
+                for (int c = 1; c < NE - 1; ++c)
+                    vv[c] = te ? re[(c - 1) * NQ * NQ] - te[(c - 1) * NQ * NQ] : re[(c - 1) * NQ * NQ];
+                vv[NE - 1] = gather(ebase + 1);
             }
         }
-        __syncthreads();  // sS, slam ready
-        // modes along c: sa[k][b][a] = sum_c Sz[c][k] v[c]
+        __syncthreads();  // sSz, slz ready
         if (act) {
+            // modes along c (rows of Sz read contiguously)
 #pragma unroll
-            for (int k = 0; k < NE; ++k) {
-                float s = 0.0f;
+            for (int k = 0; k < NE; ++k) w[k] = 0.0f;
 #pragma unroll
-                for (int c = 0; c < NE; ++c) s += sS[2][c][k] * vv[c];
-                sa[k][b][a] = s;
-            }
-        }
-        __syncthreads();
-        // modes along b: sb[k][j][a] = sum_b Sy[b][j] sa[k][b][a]   (thread (a, j))
-        if (act) {
+            for (int c = 0; c < NE; ++c)
 #pragma unroll
-            for (int k = 0; k < NE; ++k) {
-                float s = 0.0f;
+                for (int k = 0; k < NE; ++k) w[k] += sS[el][2][c][k] * vv[c];
 #pragma unroll
-                for (int bb = 0; bb < NE; ++bb) s += sS[1][bb][b] * sa[k][bb][a];
-                sb[k][b][a] = s;
-            }
-        }
-        __syncthreads();
-        // modes along a, scaled by the inverse eigenvalue sum (thread (i, j))
-        if (act) {
-#pragma unroll
-            for (int k = 0; k < NE; ++k) {
-                float s = 0.0f;
-#pragma unroll
-                for (int aa = 0; aa < NE; ++aa) s += sS[0][aa][a] * sb[k][b][aa];
-                sa[k][b][a] = s / (h1 * (slam[0][a] + slam[1][b] + slam[2][k]) + h2);
-            }
-        }
-        __syncthreads();
-        // back along a: sb[k][j][p] = sum_i Sx[p][i] sa[k][j][i]   (thread (p, j))
-        if (act) {
-#pragma unroll
-            for (int k = 0; k < NE; ++k) {
-                float s = 0.0f;
-#pragma unroll
-                for (int i = 0; i < NE; ++i) s += sS[0][a][i] * sa[k][b][i];
-                sb[k][b][a] = s;
-            }
+            for (int k = 0; k < NE; ++k) sa[el][k][b][a] = w[k];
         }
         __syncthreads();
         if (act) {
-            // back along b: w[k] = sum_j Sy[q][j] sb[k][j][p]   (thread (p, q))
+            // modes along b (thread (a, j = b))
+            float Sm[NE];
+#pragma unroll
+            for (int m = 0; m < NE; ++m) Sm[m] = sS[el][1][m][b];
 #pragma unroll
             for (int k = 0; k < NE; ++k) {
                 float s = 0.0f;
 #pragma unroll
-                for (int j = 0; j < NE; ++j) s += sS[1][b][j] * sb[k][j][a];
+                for (int m = 0; m < NE; ++m) s += Sm[m] * sa[el][k][m][a];
+                sb[el][k][b][a] = s;
+            }
+        }
+        __syncthreads();
+        if (act) {
+            // modes along a (thread (i = a, j = b)), scaled by the inverse eigenvalue sum
+            float Sm[NE];
+#pragma unroll
+            for (int m = 0; m < NE; ++m) Sm[m] = sS[el][0][m][a];
+#pragma unroll
+            for (int k = 0; k < NE; ++k) {
+                float s = 0.0f;
+#pragma unroll
+                for (int m = 0; m < NE; ++m) s += Sm[m] * sb[el][k][b][m];
+                sa[el][k][b][a] = __fdividef(s, h1 * (lxa + lyb + slz[el][k]) + h2);
+            }
+        }
+        __syncthreads();
+        if (act) {
+            // back along a (thread (p = a, j = b))
+            float Sm[NE];
+#pragma unroll
+            for (int m = 0; m < NE; ++m) Sm[m] = sS[el][0][a][m];
+#pragma unroll
+            for (int k = 0; k < NE; ++k) {
+                float s = 0.0f;
+#pragma unroll
+                for (int m = 0; m < NE; ++m) s += Sm[m] * sa[el][k][b][m];
+                sb[el][k][b][a] = s;
+            }
+        }
+        __syncthreads();
+        if (act) {
+            // back along b (thread (p, q = b)), then along c in registers
+            float Sm[NE];
+#pragma unroll
+            for (int m = 0; m < NE; ++m) Sm[m] = sS[el][1][b][m];
+#pragma unroll
+            for (int k = 0; k < NE; ++k) {
+                float s = 0.0f;
+#pragma unroll
+                for (int m = 0; m < NE; ++m) s += Sm[m] * sb[el][k][m][a];
                 w[k] = s;
             }
-            // back along c (registers) and store
-#pragma unroll
-            for (int c = 0; c < NE; ++c) {
+            float *acce = acc + e * NP + (b - 1) * NQ + (a - 1);
+            float *Ue = EXT_OUT ? U + e * NEXT : nullptr;
+            auto line = [&](int c) {
                 float s = 0.0f;
 #pragma unroll
-                for (int k = 0; k < NE; ++k) s += sS[2][c][k] * w[k];
-                U[e * NE3 + (c * NE + b) * NE + a] = s;
+                for (int k = 0; k < NE; ++k) s += sS[el][2][c][k] * w[k];
+                return s;
+            };
+            if (acol) {
+                if (EXT_OUT)
+#pragma unroll
+                    for (int c = 0; c < NE; ++c) Ue[ebase + c] = line(c);
+            } else {
+#pragma unroll
+                for (int c = 1; c < NE - 1; ++c) acce[(c - 1) * NQ * NQ] = line(c);
+                if (EXT_OUT) {
+                    Ue[ebase] = line(0);
+                    Ue[ebase + 1] = line(NE - 1);
+                }
             }
         }
     }
 }
 
-// ASM: acc[c] = sum of the local-solution entries listed for copy c, in order
-__global__ void asm_accum_kernel(int64_t nL, const int32_t *__restrict__ off,
-                                 const int32_t *__restrict__ src, const float *__restrict__ U,
-                                 int64_t ldU, float *__restrict__ acc, int64_t ld, VSet vs)
+// ASM: acc[rc[i]] += the extension results listed for that copy, in order
+__global__ void asm_ext_kernel(int64_t nrc, const int32_t *__restrict__ rc,
+                               const int32_t *__restrict__ off, const int32_t *__restrict__ src,
+                               const float *__restrict__ U, int64_t ldU, float *__restrict__ acc,
+                               int64_t ld, VSet vs)
 {
     const int64_t v = vs.at(blockIdx.y);
     U += v * ldU;
     acc += v * ld;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < nL;
-         l += (int64_t)gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        for (int q = off[l]; q < off[l + 1]; ++q) s += U[src[q]];
-        acc[l] = s;
-    }
-}
-
-// RAS: acc[copy (e, i, j, k)] = local solution of element e at its own point
-template <int NE>
-__global__ void ras_own_kernel(int64_t E, const float *__restrict__ U, float *__restrict__ acc,
-                               int64_t ld, VSet vs)
-{
-    constexpr int NQ = NE - 2, NP = NQ * NQ * NQ, NE3 = NE * NE * NE;
-    const int64_t v = vs.at(blockIdx.y);
-    U += v * E * NE3;
-    acc += v * ld;
-    const int64_t n = E * NP;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n;
-         l += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = l / NP;
-        const int p = (int)(l - e * NP);
-        const int i = p % NQ, j = (p / NQ) % NQ, k = p / (NQ * NQ);
-        acc[l] = U[e * NE3 + ((k + 1) * NE + (j + 1)) * NE + (i + 1)];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrc;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = rc[i];
+        float s = acc[c];
+        for (int q = off[i]; q < off[i + 1]; ++q) s += U[src[q]];
+        acc[c] = s;
     }
 }
 
@@ -503,27 +581,28 @@ int launch_schwarz(const Level &L, bool ras, const float *r, const float *t, flo
         return SEM_EINVAL;
     }
     const int64_t cap = (int64_t)(L.n_cu > 0 ? L.n_cu : 256) * 8;
-    const dim3 gridE((unsigned)std::min<int64_t>(L.E, cap), (unsigned)vs.n);
-    const int64_t ldU = L.E * (int64_t)L.sz_ne * L.sz_ne * L.sz_ne;
 #define SEM_FDM(NE)                                                                         \
-    case NE:                                                                                \
-        hipLaunchKernelGGL(fdm_kernel<NE>, gridE, dim3(((NE * NE + 63) / 64) * 64), 0, s, L.E, \
-                           L.sz_ix, L.sz_S, L.sz_lam, r, t, L.nL, U, (float)h1, (float)h2, vs); \
+    case NE: {                                                                              \
+        const int64_t groups = (L.E + FdmShape<NE>::EPB - 1) / FdmShape<NE>::EPB;           \
+        const dim3 grid((unsigned)std::min<int64_t>(groups, cap), (unsigned)vs.n);          \
+        if (ras)                                                                            \
+            hipLaunchKernelGGL((fdm_kernel<NE, false>), grid, dim3(256), 0, s, L.E, L.sz_ix,  \
+                               L.sz_S, L.sz_lam, r, t, L.nL, acc, U, (float)h1, (float)h2, vs); \
+        else                                                                                \
+            hipLaunchKernelGGL((fdm_kernel<NE, true>), grid, dim3(256), 0, s, L.E, L.sz_ix,   \
+                               L.sz_S, L.sz_lam, r, t, L.nL, acc, U, (float)h1, (float)h2, vs); \
         SEM_HIP(hipGetLastError());                                                         \
-        if (ras) {                                                                          \
-            hipLaunchKernelGGL(ras_own_kernel<NE>, dim3(1024, (unsigned)vs.n), dim3(256), 0, s, \
-                               L.E, U, acc, L.nL, vs);                                      \
-            SEM_HIP(hipGetLastError());                                                     \
-        }                                                                                   \
-        break
+        break;                                                                              \
+    }
     switch (L.sz_ne) {
-        SEM_FDM(5); SEM_FDM(6); SEM_FDM(7); SEM_FDM(8); SEM_FDM(9); SEM_FDM(10); SEM_FDM(11);
+        SEM_FDM(5) SEM_FDM(6) SEM_FDM(7) SEM_FDM(8) SEM_FDM(9) SEM_FDM(10) SEM_FDM(11)
     default: set_error("Schwarz smoother: unsupported order N = %d", L.N); return SEM_EINVAL;
     }
 #undef SEM_FDM
-    if (!ras) {
-        hipLaunchKernelGGL(asm_accum_kernel, dim3(1024, (unsigned)vs.n), dim3(256), 0, s, L.nL, L.sz_off,
-                           L.sz_src, (const float *)U, ldU, acc, L.nL, vs);
+    if (!ras && L.sz_nrc > 0) {
+        const int64_t ldU = L.E * (int64_t)L.sz_next;
+        hipLaunchKernelGGL(asm_ext_kernel, dim3(1024, (unsigned)vs.n), dim3(256), 0, s, L.sz_nrc, L.sz_rc,
+                           L.sz_off, L.sz_src, (const float *)U, ldU, acc, L.nL, vs);
         SEM_HIP(hipGetLastError());
     }
     return SEM_OK;

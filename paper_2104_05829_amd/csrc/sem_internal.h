@@ -132,15 +132,18 @@ struct Level {
     // element extents along r, s, t [E][3] (host), for the Schwarz smoother
     std::vector<double> len;
     // overlapping Schwarz smoother (built on first use): extended points
-    // ne = nq + 2 per direction; sz_ix [E][ne^3] copy gathered at each point
-    // (-1 absent); FDM data sz_S [E][3][ne][ne] (row = point, column = mode)
-    // and sz_lam [E][3][ne]; ASM accumulation lists sz_off [nL+1] / sz_src
-    // (indices into the local solutions [E][ne^3], ascending) and weight
-    // sz_w [nL] = mask / (subdomains containing the node)
-    int sz_ne = 0;
+    // ne = nq + 2 per direction, of which the n_ext = ne^3 - nq^3 outside the
+    // element (enumerated by schwarz_ext_slot); sz_ix [E][n_ext] copy gathered
+    // at each of them (-1 absent); FDM data sz_S [E][3][ne][ne] (row = point,
+    // column = mode) and sz_lam [E][3][ne]; ASM lists: the sz_nrc copies that
+    // receive extension values, sz_rc, with sz_off [nrc+1] / sz_src (indices
+    // into the extension results [E][n_ext], ascending); weight sz_w [nL] =
+    // mask / (subdomains containing the node)
+    int sz_ne = 0, sz_next = 0;
+    int64_t sz_nrc = 0;
     int32_t *sz_ix = nullptr;
     float *sz_S = nullptr, *sz_lam = nullptr;
-    int32_t *sz_off = nullptr, *sz_src = nullptr;
+    int32_t *sz_rc = nullptr, *sz_off = nullptr, *sz_src = nullptr;
     float *sz_w = nullptr;
     double sz_lmax = 0.0;  // lambda_max(M^{-1} A) estimate for the current key
 };
@@ -257,12 +260,26 @@ template <typename TI>
 int launch_prolong_add(const Level &F, const Level &C, const TI *in, float *x, const VSet &vs,
                        hipStream_t s);
 
+// Extended point (a, b, c) outside the element (some coordinate 0 or ne-1):
+// its slot in [0, n_ext).  Columns (a, b) on the border of the ne x ne square
+// hold ne slots each; inner columns hold their two end points.
+__host__ __device__ inline int schwarz_ext_slot(int ne, int a, int b, int c)
+{
+    int col;
+    if (b == 0) col = a;
+    else if (b == ne - 1) col = ne + a;
+    else if (a == 0) col = 2 * ne + (b - 1);
+    else if (a == ne - 1) col = 2 * ne + (ne - 2) + (b - 1);
+    else return (4 * ne - 4) * ne + ((b - 1) * (ne - 2) + (a - 1)) * 2 + (c == ne - 1 ? 1 : 0);
+    return col * ne + c;
+}
+
 // overlapping Schwarz smoother of a level (schwarz.hip): build_schwarz fills
 // the sz_* fields; launch_schwarz computes the local FDM solutions of
-// res = r - t (t nullable: res = r) for the batch vs into U [nv][E][ne^3] and
-// their combination acc [nv][nL] before QQ^T (ASM: all points through the
-// accumulation lists; RAS: each copy's own point); the caller applies QQ^T
-// and the weight (sz_w for ASM, W32 for RAS).
+// res = r - t (t nullable: res = r) for the batch vs: each element's own
+// points go to acc [nv][nL], and for ASM the extension points to U
+// [nv][E][n_ext], then added into the receiving copies of acc; the caller
+// applies QQ^T and the weight (sz_w for ASM, W32 for RAS).
 int build_schwarz(Level &L, hipStream_t s);
 void free_schwarz(Level &L);
 int launch_schwarz(const Level &L, bool ras, const float *r, const float *t, float *U, float *acc,
