@@ -555,20 +555,36 @@ fdm_kernel(int64_t E, const int32_t *__restrict__ ix, const float *__restrict__ 
 }
 
 // ASM: acc[rc[i]] += the extension results listed for that copy, in order
+// Extension values of the neighbours' local solutions added into the copies
+// that receive them, every vector of the batch in one pass over the lists: a
+// thread holds the first kAsmRegs source indices of its copy in registers
+// (a copy interior to a box of hexahedra receives from at most 7 extended
+// subdomains), so the lists are read once per call; the summation order per
+// copy is the list order for every vector.
+constexpr int kAsmRegs = 8;
+
 __global__ void asm_ext_kernel(int64_t nrc, const int32_t *__restrict__ rc,
                                const int32_t *__restrict__ off, const int32_t *__restrict__ src,
                                const float *__restrict__ U, int64_t ldU, float *__restrict__ acc,
                                int64_t ld, VSet vs)
 {
-    const int64_t v = vs.at(blockIdx.y);
-    U += v * ldU;
-    acc += v * ld;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrc;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = rc[i];
-        float s = acc[c];
-        for (int q = off[i]; q < off[i + 1]; ++q) s += U[src[q]];
-        acc[c] = s;
+        const int32_t q0 = off[i], nq = off[i + 1] - q0;
+        int32_t sq[kAsmRegs];
+#pragma unroll
+        for (int j = 0; j < kAsmRegs; ++j) sq[j] = j < nq ? src[q0 + j] : 0;
+        for (int q = 0; q < vs.n; ++q) {
+            const int64_t v = vs.at(q);
+            const float *Uv = U + v * ldU;
+            float s = acc[v * ld + c];
+#pragma unroll
+            for (int j = 0; j < kAsmRegs; ++j)
+                if (j < nq) s += Uv[sq[j]];
+            for (int j = kAsmRegs; j < nq; ++j) s += Uv[src[q0 + j]];
+            acc[v * ld + c] = s;
+        }
     }
 }
 
@@ -601,7 +617,9 @@ int launch_schwarz(const Level &L, bool ras, const float *r, const float *t, flo
 #undef SEM_FDM
     if (!ras && L.sz_nrc > 0) {
         const int64_t ldU = L.E * (int64_t)L.sz_next;
-        hipLaunchKernelGGL(asm_ext_kernel, dim3(1024, (unsigned)vs.n), dim3(256), 0, s, L.sz_nrc, L.sz_rc,
+        const int64_t groups = (L.sz_nrc + 255) / 256;
+        const unsigned g = (unsigned)std::min<int64_t>(groups, cap);
+        hipLaunchKernelGGL(asm_ext_kernel, dim3(g), dim3(256), 0, s, L.sz_nrc, L.sz_rc,
                            L.sz_off, L.sz_src, (const float *)U, ldU, acc, L.nL, vs);
         SEM_HIP(hipGetLastError());
     }
