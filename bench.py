@@ -20,6 +20,9 @@ Also reported on the same JSON line:
                 Helmholtz box (h1=1, h2=10, N=7, 3 Gaussian right-hand sides):
                 FCG with the FP32 p-multigrid (7->3->1) against FP64 Jacobi-PCG,
                 each right-hand side solved on its own and the three in lockstep
+  advection     the dealiased advection operator (Gauss rule exact for degree
+                3N) on the 32^3 deformed box, three fields per call, against the
+                HBM and FP64 peaks
 """
 from __future__ import annotations
 
@@ -37,6 +40,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GDOF/s per Ax (N=7 FP64) + PCG time-to-1e-8, mixed-prec vs FP64, %HBM peak"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6  # MI355X dense FP64 (vector and matrix)
 AX_BYTES_PER_POINT = 64  # u 8 + six G 48 + w 8 (FP64 Poisson)
 AX3_BYTES_PER_POINT = 96  # three fields: 3 x (u 8 + w 8) + six G 48 read once
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "ax_fp64_box16_n7_traffic.txt")
@@ -264,6 +268,63 @@ def bench_projection(args, torch, sem_mod, inputs):
     return out
 
 
+def advect_flops(nq, M):
+    """Flops of one element and field in the advection kernel (a multiply-add
+    counts 2): i-contractions 4 nq^3 M, j-contractions 6 M^2 nq^2, the
+    per-point derivatives, integrand and back-interpolation along k
+    M^3 (8 nq + 5), back along j 2 nq^2 M^2 and along i 2 nq^3 M."""
+    return 6 * nq ** 3 * M + 8 * nq ** 2 * M ** 2 + M ** 3 * (8 * nq + 5)
+
+
+def bench_advect(args, torch, sem_mod, inputs):
+    """Dealiased advection on the 32^3 deformed box, N = 7, on the 11-point
+    Gauss rule (the smallest exact for degree 3N): the three velocity
+    components advected by the velocity (the hyperbolic substep's operator),
+    one sem_advect call for the three fields, timed with HIP events."""
+    N, ne = 7, args.pcg_elems
+    mesh = sem_mod.box_mesh(ne, ne, ne, N, deform="cyclic", amp=0.05, bc="neumann")
+    s = sem_mod.Sem(mesh)
+    t0 = time.perf_counter()
+    M = s.advect_setup()
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    c = inputs.vortex_velocity(mesh.x.reshape(-1), mesh.y.reshape(-1), mesh.z.reshape(-1))
+    C = torch.tensor(c, device="cuda")
+    ct = s.advect_velocity(C)
+    out = torch.empty_like(C)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        s.advect(ct, C, out)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        s.advect(ct, C, out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    ev0.record(stream)
+    for _ in range(10):
+        s.advect_velocity(C, ct)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_vel = ev0.elapsed_time(ev1) / 10
+    nq, E = N + 1, s.E
+    nbytes = E * (3 * 2 * 8 * nq ** 3 + 3 * 8 * M ** 3)
+    flops = E * 3 * advect_flops(nq, M)
+    s.free()
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    tfs = flops / (ms * 1e-3) / 1e12
+    return {"workload": f"{ne}x{ne}x{ne} deformed box, N=7, Gauss rule M={M} per direction "
+                        "(exact for degree 3N), the 3 velocity components advected by the velocity "
+                        "(Taylor-Green-type vortex), one sem_advect call",
+            "E": E, "M": M, "ms_advect_3_fields": round(ms, 4), "ms_velocity_transform": round(ms_vel, 4),
+            "setup_s": round(t_setup, 3),
+            "algorithmic_bytes_per_call": nbytes, "flops_per_call": flops,
+            "achieved_GBps": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "achieved_TFLOPs_fp64": round(tfs, 2), "frac_fp64_vector_peak": round(tfs / FP64_PEAK_TFS, 4),
+            "mdof_gauss_points_per_s": round(E * M ** 3 * 3 / (ms * 1e-3) / 1e6, 1)}
+
+
 def bench_large(args, torch, sem_mod, inputs):
     """64x64x32 elements on [0,2]x[0,2]x[0,1] (cubic elements of side 1/32),
     cyclic perturbation, N=7 (67,108,864 local points), Poisson (h2 = 0),
@@ -442,6 +503,7 @@ def main():
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-schwarz", action="store_true", help="skip the CHEBY-ASM / CHEBY-RAS solves")
     ap.add_argument("--no-small", action="store_true", help="skip the 4^3 and adjoint records")
+    ap.add_argument("--no-advect", action="store_true", help="skip the dealiased advection record")
     ap.add_argument("--pcg-elems", type=int, default=32)
     ap.add_argument("--pcg-rhs", type=int, default=3)
     ap.add_argument("--pcg-precond", choices=("both", "pmg", "jacobi"), default="both")
@@ -538,6 +600,9 @@ def main():
     if not args.no_pcg:
         log("[bench] projection: 10-load sequence, p-MG from zero vs projected guesses")
         line["projection"] = bench_projection(args, torch, sem_mod, inputs)
+    if not args.no_advect:
+        log("[bench] advection: 32^3 deformed box, N=7, M=11, three fields")
+        line["advection"] = bench_advect(args, torch, sem_mod, inputs)
     if not args.no_small:
         log("[bench] 4^3 Poisson Jacobi-PCG and 8^3 adjoint")
         line["c1"] = bench_c1(args, torch, sem_mod, inputs, not args.no_cpu)

@@ -350,6 +350,46 @@ SEM_API int sem_get_weights(sem_handle h, int level, double *W, int64_t *gid, vo
  * library, on the host (any output may be NULL).  No device work. */
 SEM_API int sem_gll(int N, double *xi, double *rho, double *D);
 
+/*
+ * Dealiased advection (the advection term u . grad w of the EXT formulation
+ * and of the characteristics subproblem, Sec. 2.1 eqs. (stdadv), (hyp); its
+ * degree-3N integrand needs a quadrature finer than GLL, Sec. 2.3; the
+ * advection kernels of Sec. 3.3).  Level 0 only, FP64.  The weak form
+ * (v, c . grad w) on each element is evaluated on the M-point Gauss-Legendre
+ * rule per direction (M^3 points):
+ *   ct_q  = rho~ |det X| (dr_q/dx . J3 c),  q = r, s, t   (contravariant
+ *           weighted velocity at the Gauss points; X = dx/dr of the
+ *           interpolated element map, rho~ the products of Gauss weights)
+ *   out_e = J3^T ( sum_q ct_q  d_q (J3 w_e) )
+ * with J3 = J (x) J (x) J the interpolation from the GLL points to the Gauss
+ * points and d_q the derivative of the interpolant along r_q, so that
+ * v_L . out_L = sum over elements and Gauss points of rho~ |det X| v c.grad w,
+ * exact for polynomial integrands of degree <= 2M - 1 per variable.
+ *
+ * sem_advect_setup: builds J, Jd and the metric factors for the rule
+ *   (M = 0: the smallest rule exact for degree 3N, M = ceil((3N+1)/2)); M must
+ *   be N+1..16 and, for the compiled kernels, one of the two rules
+ *   ceil((3N+1)/2) or ceil((3N+1)/2) + 1, with N <= 7; *M_used (nullable)
+ *   receives M.  Device memory 72 M^3 bytes per element (freed by sem_free or
+ *   a new setup).  Synchronises `stream`.  SEM_EMESH if det X <= 0 at a Gauss
+ *   point.
+ * sem_advect_velocity: ct [E][3][M^3] (point index a + M b + M^2 c, a along r)
+ *   from the velocity c (three level-0 L-vectors at c + d * ldc, d = x, y, z;
+ *   ldc >= n_local).  ct is caller-owned device memory of 3 E M^3 doubles and
+ *   may be reused for any number of advected fields.
+ * sem_advect: out (nf L-vectors at out + f * ldo) = the local (unassembled)
+ *   advection of the nf fields at w + f * ldw by ct; 0 <= nf <= SEM_MAX_RHS
+ *   (nf = 0 does nothing); ldw, ldo >= n_local when nf > 1; out may not alias
+ *   w or ct.  Apply sem_gs for the assembled form and the inverse assembled
+ *   mass for the strong form of the hyperbolic substep.
+ * All three are asynchronous on `stream` except the setup; errors:
+ *   SEM_EINVAL (null handle or pointer, setup missing, unsupported M or nf).
+ */
+SEM_API int sem_advect_setup(sem_handle h, int M, int *M_used, void *stream);
+SEM_API int sem_advect_velocity(sem_handle h, const double *c, int64_t ldc, double *ct, void *stream);
+SEM_API int sem_advect(sem_handle h, const double *ct, int nf, const double *w, int64_t ldw,
+                       double *out, int64_t ldo, void *stream);
+
 SEM_API const char *sem_strerror(int code);
 SEM_API const char *sem_last_error(void);
 

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsem.so")
 ARCH = os.environ.get("SEM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "ax_f64.hip", "ax_f32.hip", "ops.hip", "maps.hip", "solve.hip", "schwarz.hip",
+SOURCES = ["api.hip", "ax_f64.hip", "ax_f32.hip", "ops.hip", "maps.hip", "solve.hip", "schwarz.hip", "advect.hip",
            "gll.cpp"]
 
 CFLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

@@ -302,6 +302,12 @@ static int setup_impl(const sem_mesh *m, const sem_setup_opts *o, hipStream_t s,
             rc = SEM_EMESH;
         }
     } while (0);
+    if (rc == SEM_OK) {  // the handle keeps the level-0 coordinates
+        h->cx = x;
+        h->cy = y;
+        h->cz = z;
+        x = y = z = nullptr;
+    }
     if (x) (void)hipFree(x);
     if (y) (void)hipFree(y);
     if (z) (void)hipFree(z);
@@ -391,6 +397,10 @@ int sem_free(sem_handle h)
     (void)hipSetDevice(h->device);
     free_workspace(h);
     for (int l = 0; l < kMaxLevels; ++l) free_level(h->lv[l]);
+    free_advect(h);
+    void *coords[] = {h->cx, h->cy, h->cz};
+    for (void *p : coords)
+        if (p) (void)hipFree(p);
     (void)hipSetDevice(cur);
     delete h;
     return SEM_OK;

@@ -112,4 +112,43 @@ void host_interp(int ns, const double *xs, int nt, const double *xt, double *J)
     }
 }
 
+// Gauss--Legendre rule with M points on [-1, 1], ascending: the zeros of P_M
+// by Newton's method from the start points cos(pi (j + 3/4) / (M + 1/2)),
+// weights 2 / ((1 - x^2) P_M'(x)^2).
+int host_gauss(int M, double *x, double *w)
+{
+    if (M < 1 || M > kMaxGauss) return SEM_EINVAL;
+    for (int j = 0; j < M; ++j) {
+        double t = -std::cos(M_PI * (j + 0.75) / (M + 0.5));
+        double pn = 0.0, pn1 = 0.0, dpn = 0.0, dpn1 = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            if (M == 1) {
+                t = 0.0;
+                break;
+            }
+            legendre_pair(M, t, pn, pn1, dpn, dpn1);
+            const double step = pn / dpn;
+            t -= step;
+            if (std::fabs(step) <= 1e-16 * (1.0 + std::fabs(t))) break;
+        }
+        x[j] = t;
+    }
+    for (int j = 0; j < M / 2; ++j) {  // symmetric rule
+        const double a = 0.5 * (x[M - 1 - j] - x[j]);
+        x[j] = -a;
+        x[M - 1 - j] = a;
+    }
+    if (M % 2 == 1) x[M / 2] = 0.0;
+    for (int j = 0; j < M; ++j) {
+        double dp = 1.0;
+        if (M > 1) {
+            double pn, pn1, dpn, dpn1;
+            legendre_pair(M, x[j], pn, pn1, dpn, dpn1);
+            dp = dpn;
+        }
+        w[j] = 2.0 / ((1.0 - x[j] * x[j]) * dp * dp);
+    }
+    return SEM_OK;
+}
+
 }  // namespace semx

@@ -30,6 +30,8 @@ void set_error(const char *fmt, ...);
     } while (0)
 
 constexpr int kMaxN = 15;
+// largest Gauss rule of the dealiased advection operator (M^2 threads per element)
+constexpr int kMaxGauss = 16;
 // largest number of workgroups per CU of the persistent element-operator grid
 // (the operator's partial-sum buffer holds one value per workgroup)
 constexpr int kAxMaxBlocksPerCU = 16;
@@ -201,6 +203,15 @@ struct sem_handle_s {
     int device = 0;
     int n_levels = 0;
     semx::Level lv[semx::kMaxLevels];
+    // level-0 coordinates [nL] each (kept for the advection metrics)
+    double *cx = nullptr, *cy = nullptr, *cz = nullptr;
+    // dealiased advection on the M-point Gauss rule: interpolation J and
+    // derivative Jd = J Dh [M][nq], weights wq [M], metric factors
+    // F [E][9][M^3] = rho~ |det X| dr_q/dx_d at index 3 q + d
+    struct Advect {
+        int M = 0;
+        double *J = nullptr, *Jd = nullptr, *wq = nullptr, *F = nullptr;
+    } adv;
     semx::Workspace ws;
     semx::PrecondKey key;
     uint64_t lanczos_seed = 0x5eed5eedULL;
@@ -282,6 +293,7 @@ __host__ __device__ inline int schwarz_ext_slot(int ne, int a, int b, int c)
 // applies QQ^T and the weight (sz_w for ASM, W32 for RAS).
 int build_schwarz(Level &L, hipStream_t s);
 void free_schwarz(Level &L);
+void free_advect(sem_handle h);
 int launch_schwarz(const Level &L, bool ras, const float *r, const float *t, float *U, float *acc,
                    const VSet &vs, double h1, double h2, hipStream_t s);
 
@@ -292,6 +304,7 @@ int build_gs_chunks(Level &L, hipStream_t s);
 
 int host_gll(int N, double *xi, double *rho, double *D);
 void host_interp(int ns, const double *xs, int nt, const double *xt, double *J);
+int host_gauss(int M, double *x, double *w);
 
 // solver entry (solve.hip)
 int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld,

@@ -179,6 +179,17 @@ def sin3(x, y, z) -> np.ndarray:
     return np.sin(math.pi * x) * np.sin(math.pi * y) * np.sin(math.pi * z)
 
 
+def vortex_velocity(x, y, z):
+    """A divergence-free velocity tangential to the faces of the unit cube (a
+    Taylor-Green-type vortex), returned as a [3, ...] array:
+    (sin pi x cos pi y cos pi z, cos pi x sin pi y cos pi z,
+     -2 cos pi x cos pi y sin pi z)."""
+    px, py, pz = (math.pi * np.asarray(a, dtype=np.float64) for a in (x, y, z))
+    return np.stack([np.sin(px) * np.cos(py) * np.cos(pz),
+                     np.cos(px) * np.sin(py) * np.cos(pz),
+                     -2.0 * np.cos(px) * np.cos(py) * np.sin(pz)])
+
+
 def load_sequence(gid: np.ndarray, n_steps: int, seed: int = 60, period: float = 40.0,
                   eps: float = 1e-3):
     """Loads f_n for a sequence of solves with slowly varying right-hand sides

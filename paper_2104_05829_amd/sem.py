@@ -99,6 +99,9 @@ _SIGS = {
                                               _VP, _VP, _VP]),
     "sem_smoother_apply": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                           ctypes.c_double, _VP, _VP, _VP]),
+    "sem_advect_setup": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _VP]),
+    "sem_advect_velocity": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP, _VP]),
+    "sem_advect": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP, ctypes.c_int64, _VP, ctypes.c_int64, _VP]),
     "sem_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(SemSolveOpts),
                                      ctypes.POINTER(SemSolveStats), _VP]),
     "sem_grad_k": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
@@ -443,6 +446,51 @@ class Sem:
                                         _dev_ptr(r, torch.float32, n, "r"), _dev_ptr(z, torch.float32, n, "z"),
                                         _stream()), "sem_smoother_apply")
         return z
+
+    # -- dealiased advection ----------------------------------------------
+    def advect_setup(self, M=None):
+        """Metric factors for the M-point Gauss rule (None: the smallest rule
+        exact for degree 3N); returns M."""
+        m = ctypes.c_int(0)
+        _check(lib().sem_advect_setup(self._handle(), int(M or 0), ctypes.byref(m), _stream()),
+               "sem_advect_setup")
+        self.adv_m = int(m.value)
+        return self.adv_m
+
+    def advect_velocity(self, C, ct=None):
+        """Contravariant weighted velocity [E, 3, M^3] at the Gauss points for
+        the velocity C ([3, n_local] FP64, rows x, y, z)."""
+        torch = _torch()
+        M = getattr(self, "adv_m", 0)
+        if not M:
+            raise SemError(SEM_EINVAL, "advect_velocity: call advect_setup first")
+        pc, nr, ldc = _dev_batch(C, torch.float64, self.n_local, "C")
+        if nr != 3:
+            raise ValueError("C must have 3 rows (x, y, z components)")
+        if ct is None:
+            ct = torch.empty((self.E, 3, M ** 3), dtype=torch.float64, device=C.device)
+        pt = _dev_ptr(ct, torch.float64, self.E * 3 * M ** 3, "ct")
+        _check(lib().sem_advect_velocity(self._handle(), pc, ldc, pt, _stream()), "sem_advect_velocity")
+        return ct
+
+    def advect(self, ct, W, out=None):
+        """Local dealiased advection of the rows of W ([nf, n_local] or
+        [n_local], FP64) by ct (from advect_velocity)."""
+        torch = _torch()
+        M = getattr(self, "adv_m", 0)
+        single = W.dim() == 1
+        W2 = W.unsqueeze(0) if single else W
+        if out is None:
+            out = torch.empty_like(W2)
+        O2 = out.unsqueeze(0) if out.dim() == 1 else out
+        pw, nf, ldw = _dev_batch(W2, torch.float64, self.n_local, "W")
+        po, nfo, ldo = _dev_batch(O2, torch.float64, self.n_local, "out")
+        if nfo != nf:
+            raise ValueError("W and out must have the same number of rows")
+        pt = _dev_ptr(ct, torch.float64, self.E * 3 * M ** 3 if M else None, "ct")
+        _check(lib().sem_advect(self._handle(), pt, nf, pw, max(ldw, self.n_local), po,
+                                max(ldo, self.n_local), _stream()), "sem_advect")
+        return O2[0] if single else O2
 
     def proj_reset(self):
         """Forget the stored solutions of the projected initial guesses."""

@@ -80,3 +80,24 @@ def test_load_sequence_recipe():
         ref = g0 + np.sin(2 * np.pi * t) * g1 + t * t * g2 + 0.01 * I.gaussian_per_node(m.gid, 8 + n)
         np.testing.assert_allclose(seq[n], ref, rtol=0, atol=1e-15)
     assert all(f.shape == (m.n_local,) for f in seq)
+
+
+def test_vortex_velocity_is_solenoidal_and_tangential():
+    """The advection test velocity: zero divergence (central differences) and
+    zero normal component on the unit cube's faces."""
+    rng = np.random.default_rng(0)
+    p = rng.uniform(0.05, 0.95, (3, 50))
+    h = 1e-6
+    div = 0.0
+    for d in range(3):
+        e = np.zeros((3, 1))
+        e[d] = h
+        div = div + (inputs.vortex_velocity(*(p + e))[d] - inputs.vortex_velocity(*(p - e))[d]) / (2 * h)
+    assert np.max(np.abs(div)) < 1e-8
+    t = rng.uniform(0, 1, (2, 20))
+    for d in range(3):
+        for side in (0.0, 1.0):
+            q = np.empty((3, 20))
+            q[d] = side
+            q[[a for a in range(3) if a != d]] = t
+            assert np.max(np.abs(inputs.vortex_velocity(*q)[d])) < 1e-15
