@@ -90,18 +90,19 @@ __device__ __forceinline__ void stage_cols(const double *Jb, const double *Jdb, 
 }
 
 template <int NQ, int M>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__((AdvShape<NQ, M>::THREADS)) __attribute__((amdgpu_waves_per_eu(1, 8)))
     advect_kernel(int64_t E, const double *__restrict__ J, const double *__restrict__ Jd,
                   const double *__restrict__ ct, int nf, const double *__restrict__ w, int64_t ldw,
                   double *__restrict__ out, int64_t ldo)
 {
     using S = AdvShape<NQ, M>;
+    constexpr int NP = S::NP, MM = S::MM, M3 = S::M3, TH = S::THREADS;
     __shared__ double sA[S::SA];
     __shared__ double sB[S::SB];
     double *sP = sA, *sQ = sA + NQ * NQ * M, *sG = sA;
     double *sU = sB, *sH = sB;
     const int t = threadIdx.x;
-    const bool col = t < S::MM;
+    const bool col = t < MM;
     const int a = col ? t % M : 0, b = col ? t / M : 0;
     double Jb[NQ], Jdb[NQ];
 #pragma unroll
@@ -109,27 +110,90 @@ __global__ void __launch_bounds__(256)
         Jb[j] = J[b * NQ + j];
         Jdb[j] = Jd[b * NQ + j];
     }
+    // the next field (or the next element's first field) is loaded into
+    // registers while the current one is computed
+    constexpr int PFN = (NP + TH - 1) / TH;
+    double un[PFN];
+    if (blockIdx.x < E) {
+#pragma unroll
+        for (int q = 0; q < PFN; ++q) {
+            const int i = t + q * TH;
+            un[q] = i < NP ? w[blockIdx.x * (int64_t)NP + i] : 0.0;
+        }
+    }
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         double c0[M], c1[M], c2[M];
-        if (col) {
-            const double *cte = ct + e * 3 * S::M3 + t;
-#pragma unroll
-            for (int c = 0; c < M; ++c) {
-                c0[c] = cte[c * S::MM];
-                c1[c] = cte[S::M3 + c * S::MM];
-                c2[c] = cte[2 * S::M3 + c * S::MM];
-            }
-        }
         for (int f = 0; f < nf; ++f) {
-            const double *u = w + f * ldw + e * S::NP;
-            for (int i = t; i < S::NP; i += blockDim.x) sU[i] = u[i];
+#pragma unroll
+            for (int q = 0; q < PFN; ++q) {
+                const int i = t + q * TH;
+                if (i < NP) sU[i] = un[q];
+            }
+            if (f == 0 && col) {  // issued after the staged field, consumed two stages later
+                const double *cte = ct + e * 3 * M3 + t;
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    c0[c] = cte[c * MM];
+                    c1[c] = cte[M3 + c * MM];
+                    c2[c] = cte[2 * M3 + c * MM];
+                }
+            }
+            {
+                int64_t en = e;
+                int fn = f + 1;
+                if (fn == nf) {
+                    fn = 0;
+                    en = e + gridDim.x;
+                }
+                if (en < E) {
+                    const double *src = w + fn * ldw + en * NP;
+#pragma unroll
+                    for (int q = 0; q < PFN; ++q) {
+                        const int i = t + q * TH;
+                        un[q] = i < NP ? src[i] : 0.0;
+                    }
+                }
+            }
             __syncthreads();
-            stage_rows<NQ, M>(J, Jd, sU, sP, sQ, true);
+            // contraction over i on GLL rows (k, j)
+            if (t < NQ * NQ) {
+                const int j = t % NQ, k = t / NQ;
+                double r[NQ];
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) r[i] = sU[(k * NQ + j) * NQ + i];
+#pragma unroll
+                for (int a2 = 0; a2 < M; ++a2) {
+                    double p = 0.0, q = 0.0;
+#pragma unroll
+                    for (int i = 0; i < NQ; ++i) {
+                        p += J[a2 * NQ + i] * r[i];
+                        q += Jd[a2 * NQ + i] * r[i];
+                    }
+                    sP[(k * NQ + j) * M + a2] = p;
+                    sQ[(k * NQ + j) * M + a2] = q;
+                }
+            }
             __syncthreads();
             double G[NQ];
             if (col) {
+                // contraction over j on the lane's Gauss column
                 double Tr[NQ], Ts[NQ], Tt[NQ];
-                stage_cols<NQ, M>(Jb, Jdb, a, sP, sQ, Tr, Ts, Tt);
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) {
+                    double xr = 0.0, xs = 0.0, xt = 0.0;
+#pragma unroll
+                    for (int j = 0; j < NQ; ++j) {
+                        const double p = sP[(k * NQ + j) * M + a], q = sQ[(k * NQ + j) * M + a];
+                        xr += Jb[j] * q;
+                        xs += Jdb[j] * p;
+                        xt += Jb[j] * p;
+                    }
+                    Tr[k] = xr;
+                    Ts[k] = xs;
+                    Tt[k] = xt;
+                }
+                // over k: derivatives at the Gauss points, integrand, and the
+                // transposed interpolation back along k, point by point
 #pragma unroll
                 for (int k = 0; k < NQ; ++k) G[k] = 0.0;
 #pragma unroll
@@ -181,7 +245,7 @@ __global__ void __launch_bounds__(256)
                 for (int a2 = 0; a2 < M; ++a2)
 #pragma unroll
                     for (int i = 0; i < NQ; ++i) o[i] += J[a2 * NQ + i] * h[a2];
-                double *op = out + f * ldo + e * S::NP + (k * NQ + j) * NQ;
+                double *op = out + f * ldo + e * NP + (k * NQ + j) * NQ;
 #pragma unroll
                 for (int i = 0; i < NQ; ++i) op[i] = o[i];
             }
@@ -352,7 +416,10 @@ int launch_fine_eval(const Level &L, int M, bool grad, const double *J, const do
 int launch_advect(const Level &L, int M, const double *J, const double *Jd, const double *ct, int nf,
                   const double *w, int64_t ldw, double *out, int64_t ldo, hipStream_t s)
 {
-    const dim3 grid((unsigned)adv_grid(L));
+    // 16 workgroups per CU (measured at N = 7, M = 11: 4 per CU 712 us, 16 per
+    // CU 623 us for three fields on 32^3 elements)
+    const int64_t cap = (int64_t)(L.n_cu > 0 ? L.n_cu : 256) * 16;
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(L.E, cap)));
 #define SEM_ADV(NQ_, M_)                                                                             \
     if (L.nq == NQ_ && M == M_) {                                                                    \
         hipLaunchKernelGGL((advect_kernel<NQ_, M_>), grid, dim3(AdvShape<NQ_, M_>::THREADS), 0, s,   \
