@@ -554,7 +554,6 @@ fdm_kernel(int64_t E, const int32_t *__restrict__ ix, const float *__restrict__ 
     }
 }
 
-// ASM: acc[rc[i]] += the extension results listed for that copy, in order
 // Extension values of the neighbours' local solutions added into the copies
 // that receive them, every vector of the batch in one pass over the lists: a
 // thread holds the first kAsmRegs source indices of its copy in registers
