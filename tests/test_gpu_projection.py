@@ -134,3 +134,44 @@ def test_projection_reset_rules_and_errors():
     with pytest.raises(SemError):
         s.solve(b, proj_dim=2, k=torch.ones_like(b))
     s.free()
+
+
+def test_full_size_projected_sequence():
+    """The benchmark's projection workload at full size (32^3 deformed
+    Helmholtz box, N = 7, FCG + FP32 p-MG to 1e-8, loads of
+    inputs.load_sequence with period 40 and eps 1e-3), four loads: the space
+    grows by one solution per solve, every solve reaches the tolerance with
+    the oracle recomputing the true residual of the last one in FP64 on the
+    whole mesh, later solves need fewer iterations than from zero, and each
+    solution agrees with the from-zero solution to the solver tolerance."""
+    import math
+    print("[gpu] projection 32^3 sequence", flush=True)
+    N, h2, tol = 7, 10.0, 1e-8
+    m = _mesh((32, 32, 32), N, deform="cyclic", amp=0.05)
+    s = Sem(m, levels=(7, 3, 1))
+    W = 1.0 - m.dirichlet.reshape(-1).astype(np.float64)
+    loads = inputs.load_sequence(m.gid, 4, seed=60, period=40.0, eps=1e-3)
+    Wd = _dev(W / oracle.multiplicity(m.gid))
+    last = None
+    for n, f in enumerate(loads):
+        b = s.rhs(_dev(f)) * _dev(W)
+        x0, st0, rc0 = s.solve(b, tol=tol, h2=h2, precond="pmg")
+        x, st, rc = s.solve(b, tol=tol, h2=h2, precond="pmg", proj_dim=8)
+        assert rc == 0 and rc0 == 0 and st["converged"], (n, st)
+        assert st["proj_vectors"] == n, (n, st)
+        assert st["true_rel_res"] <= 1.5e-8, (n, st)
+        if n >= 2:
+            assert st["iters"] < st0["iters"], (n, st["iters"], st0["iters"])
+        d = float(torch.sqrt(torch.sum(Wd * (x - x0) ** 2) / torch.sum(Wd * x0 ** 2)))
+        assert d <= 1e-6, (n, d)
+        last = (b, x, st)
+    b, x, st = last
+    Xh, Bh = _host(x), _host(b)
+    G, Bm, _ = oracle.geometry(N, m.x, m.y, m.z)
+    xi, _ = oracle.gll(N)
+    Dh = oracle.dhat(N, xi)
+    Wc = W / oracle.multiplicity(m.gid)
+    res = W * (Bh - oracle.qqt(m.gid, oracle.ax(N, Dh, G, Xh, h1=1.0, h2=h2, B=Bm)))
+    rel = math.sqrt(np.sum(Wc * res * res) / np.sum(Wc * Bh * Bh))
+    assert rel <= 1.5e-8 and abs(rel - st["true_rel_res"]) <= 1e-3 * rel + 1e-12, (rel, st)
+    s.free()

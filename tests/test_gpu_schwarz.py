@@ -147,3 +147,50 @@ def test_cheby_asm_lockstep_and_rotated_elements():
         ref = rot(Xh[r]).reshape(-1)
         assert np.max(np.abs(Xrh[r] - ref)) <= 1e-7 * np.max(np.abs(ref))
     sr.free()
+
+
+def _sub_box(m, lo, hi):
+    """The elements lo[d] <= e_d <= hi[d] of a box mesh as a mesh of their own,
+    keeping coordinates, global pointers and Dirichlet flags."""
+    Ex, Ey, Ez = m.shape
+    idx = [ex + Ex * (ey + Ey * ez) for ez in range(lo[2], hi[2] + 1) for ey in range(lo[1], hi[1] + 1)
+           for ex in range(lo[0], hi[0] + 1)]
+    idx = np.asarray(idx)
+    shape = tuple(hi[d] - lo[d] + 1 for d in range(3))
+    return idx, inputs.BoxMesh(N=m.N, shape=shape, x=m.x[idx], y=m.y[idx], z=m.z[idx], gid=m.gid[idx],
+                               dirichlet=m.dirichlet[idx])
+
+
+@pytest.mark.parametrize("variant", ["asm", "ras"])
+def test_full_size_sampled_smoother_apply(variant):
+    """32^3 deformed box, N = 7 (level 0 of the bench's 7 -> 3 -> 1 handle):
+    the smoother output on sampled elements (a corner, an edge, a face and an
+    interior one) against the oracle's Schwarz operator built on the 5x5x5
+    block of the same mesh around each (clipped at the domain boundary).  The
+    output on an element's nodes depends only on the subdomains of the
+    elements within one layer of it, whose data in turn involve only their
+    own neighbours, so the block reproduces it exactly."""
+    print(f"[gpu] schwarz apply 32^3 sampled {variant}", flush=True)
+    N, ne = 7, 32
+    m = _mesh((ne, ne, ne), N, deform="cyclic")
+    s = Sem(m, levels=(7, 3, 1))
+    rng = np.random.default_rng(12)
+    r = inputs.gaussian_per_node(m.gid, 21) * (1.0 - m.dirichlet.reshape(-1))
+    r32 = r.astype(np.float32)
+    z = _host(s.smoother_apply(0, torch.tensor(r32, device="cuda"), smoother=variant, h1=1.0, h2=10.0))
+    s.free()
+    np_ = (N + 1) ** 3
+    samples = [(0, 0, 0), (ne - 1, 0, 5), (7, ne - 1, 13), tuple(int(v) for v in rng.integers(2, ne - 2, 3))]
+    for c in samples:
+        lo = [max(0, c[d] - 2) for d in range(3)]
+        hi = [min(ne - 1, c[d] + 2) for d in range(3)]
+        idx, sub = _sub_box(m, lo, hi)
+        lv = solvers.Level(N, sub.x, sub.y, sub.z, sub.gid, sub.dirichlet, 1.0, 10.0)
+        O = asm.Schwarz(lv, sub.shape, sub.x, sub.y, sub.z, sub.dirichlet, variant)
+        rsub = r32.reshape(m.E, np_)[idx].reshape(-1).astype(np.float64)
+        ref = O.apply(rsub).reshape(len(idx), np_)
+        e0 = c[0] + ne * (c[1] + ne * c[2])
+        k = int(np.nonzero(idx == e0)[0][0])
+        got = z.reshape(m.E, np_)[e0]
+        scale = np.max(np.abs(ref))
+        assert np.max(np.abs(got - ref[k])) <= 2e-5 * scale, (c, np.max(np.abs(got - ref[k])) / scale)
