@@ -119,6 +119,7 @@ struct Level {
     // wavefront chunks of whole segments for the gather-scatter kernel
     int64_t nchunks = 0, nover = 0;
     int32_t *chunk_b = nullptr, *chunk_e = nullptr;  // perm range of each chunk
+    int32_t *chunk_perm = nullptr;                    // [nchunks][64] perm slice per lane, -1 past the end
     uint64_t *chunk_mask = nullptr;                   // segment-start lanes
     int32_t *over = nullptr;                          // segments longer than 64 copies
     double *D = nullptr;   // Dh [nq][nq] (row = point)
