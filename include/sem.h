@@ -192,6 +192,11 @@ typedef struct {
                             1 / (subdomains containing the node); needs N >= 2 on every
                             smoothed level and a conforming hex mesh; the Chebyshev
                             interval uses the power-method lambda_max of M^{-1} A */
+    int use_graphs;      /* must be 0 (kernels launched one by one).  1 would replay each
+                            V-cycle of the outer FCG from a captured HIP graph; that
+                            path is switched off (SEM_EINVAL) because one replay was
+                            seen to differ from the kernel-by-kernel solve with no
+                            cause found. */
 } sem_solve_opts;
 
 typedef struct {
@@ -209,7 +214,7 @@ typedef struct {
 /* Fill opts with defaults: h1 = 1, h2 = 0, k = NULL, tol = 1e-8, maxit = 1000,
  * Jacobi, check_every = 8, cheb_degree = 2, lanczos_steps = 20,
  * interval [0.1, 1.1] lambda_max, coarse_tol = 1e-2, coarse_maxit = 20,
- * zero_guess = 1, proj_dim = 0, smoother = SEM_SMOOTH_JACOBI. */
+ * zero_guess = 1, proj_dim = 0, smoother = SEM_SMOOTH_JACOBI, use_graphs = 0. */
 SEM_API void sem_solve_opts_default(sem_solve_opts *opts);
 
 /*

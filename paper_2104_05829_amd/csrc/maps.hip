@@ -200,20 +200,6 @@ int build_maps(Level &L, const int64_t *gid, const uint8_t *dir, const double *x
     return build_gs_chunks(L, s);
 }
 
-// lane l of chunk c: its copy perm[cb[c] + l], with kGsSegStart set when
-// the copy starts a segment (bit l of cmask[c]), or -1 past the chunk's end
-__global__ void chunk_perm_kernel(int64_t nch, const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
-                                  const uint64_t *__restrict__ cmask, const int32_t *__restrict__ perm,
-                                  int32_t *__restrict__ out)
-{
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nch * 64) return;
-    const int64_t c = g / 64;
-    const int l = (int)(g % 64);
-    const int32_t start = ((cmask[c] >> l) & 1ULL) ? kGsSegStart : 0;
-    out[g] = l < ce[c] - cb[c] ? (perm[cb[c] + l] | start) : -1;
-}
-
 // Pack whole segments, in canonical order, into chunks of at most 64 copies
 // (one wavefront each): chunk c covers perm[cstart[c] .. cstart[c+1]) and
 // bit l of cmask[c] marks lane l as the first copy of a segment.  Segments
@@ -221,10 +207,6 @@ __global__ void chunk_perm_kernel(int64_t nch, const int32_t *__restrict__ cb, c
 // segment.  Greedy on the host: O(segments), setup only.
 int build_gs_chunks(Level &L, hipStream_t s)
 {
-    if (L.nL >= (int64_t)kGsSegStart) {  // copy indices share their word with the segment-start flag
-        set_error("setup: %lld local points exceed the gather-scatter limit of 2^30", (long long)L.nL);
-        return SEM_EINVAL;
-    }
     std::vector<int32_t> offs(L.nseg + 1);
     if (L.nseg > 0)
         SEM_HIP(hipMemcpy(offs.data(), L.offs, sizeof(int32_t) * (L.nseg + 1), hipMemcpyDeviceToHost));
@@ -269,15 +251,12 @@ int build_gs_chunks(Level &L, hipStream_t s)
         SEM_HIP(hipMemcpy(L.chunk_b, cb.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice));
         SEM_HIP(hipMemcpy(L.chunk_e, ce.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice));
         SEM_HIP(hipMemcpy(L.chunk_mask, cmask.data(), sizeof(uint64_t) * nch, hipMemcpyHostToDevice));
-        SEM_HIP(hipMalloc(&L.chunk_perm, sizeof(int32_t) * nch * 64));
-        hipLaunchKernelGGL(chunk_perm_kernel, dim3((unsigned)((nch * 64 + 255) / 256)), dim3(256), 0, s, nch,
-                           L.chunk_b, L.chunk_e, L.chunk_mask, L.perm, L.chunk_perm);
-        SEM_HIP(hipGetLastError());
     }
     if (L.nover > 0) {
         SEM_HIP(hipMalloc(&L.over, sizeof(int32_t) * L.nover));
         SEM_HIP(hipMemcpy(L.over, over.data(), sizeof(int32_t) * L.nover, hipMemcpyHostToDevice));
     }
+    (void)s;
     return SEM_OK;
 }
 

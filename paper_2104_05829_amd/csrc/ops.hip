@@ -32,8 +32,9 @@ constexpr int kGsWavesPerBlock = 4;
 // applied to every vector of the batch in turn.
 template <typename T>
 __global__ void __launch_bounds__(64 * kGsWavesPerBlock)
-gs_chunk_kernel(int64_t nchunks, const int32_t *__restrict__ cperm, T *__restrict__ v, int64_t ld, VSet vs,
-                const int *__restrict__ skip, int skip_stride)
+gs_chunk_kernel(int64_t nchunks, const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
+                const uint64_t *__restrict__ cmask, const int32_t *__restrict__ perm,
+                T *__restrict__ v, int64_t ld, VSet vs, const int *__restrict__ skip, int skip_stride)
 {
     uint32_t pack;
     const int na = live_vectors(vs, skip, skip_stride, &pack);
@@ -41,14 +42,11 @@ gs_chunk_kernel(int64_t nchunks, const int32_t *__restrict__ cperm, T *__restric
     const int lane = threadIdx.x & 63;
     const int64_t c = xcd_chunk_block(blockIdx.x, gridDim.x) * kGsWavesPerBlock + (threadIdx.x >> 6);
     if (c >= nchunks) return;  // uniform per wavefront
-    // one load per lane ahead of the values: its copy, flagged at segment
-    // starts (-1 past the chunk's end); chunk size and segment starts follow
-    // by ballots
-    const int ent = cperm[c * 64 + lane];
-    const bool act = ent >= 0;
-    const int idx = act ? (ent & (kGsSegStart - 1)) : 0;
-    const uint64_t m = __ballot(act && (ent & kGsSegStart));  // bit l: lane l starts a segment (bit 0 set)
-    const int cnt = __popcll(__ballot(act));  // the chunk's copies are lanes 0 .. cnt-1
+    const int b = cb[c];
+    const int cnt = ce[c] - b;
+    const bool act = lane < cnt;
+    const int idx = act ? perm[b + lane] : 0;
+    const uint64_t m = cmask[c];  // bit l: lane l starts a segment (bit 0 always set)
     const uint64_t upto = (lane == 63) ? ~0ULL : ((2ULL << lane) - 1ULL);
     const int s0 = 63 - __clzll((long long)(m & upto));      // first lane of my segment
     const uint64_t above = m & ~upto;
@@ -99,7 +97,8 @@ int launch_gs_multi(const Level &L, T *v, int64_t ld, const VSet &vs, hipStream_
     if (L.nchunks > 0) {
         const int64_t nb = (L.nchunks + kGsWavesPerBlock - 1) / kGsWavesPerBlock;
         hipLaunchKernelGGL(gs_chunk_kernel<T>, dim3((unsigned)nb), dim3(64 * kGsWavesPerBlock), 0, s,
-                           L.nchunks, L.chunk_perm, v, ld, vs, skip, skip_stride);
+                           L.nchunks, L.chunk_b, L.chunk_e, L.chunk_mask, L.perm, v, ld, vs, skip,
+                           skip_stride);
         SEM_HIP(hipGetLastError());
     }
     if (L.nover > 0) {

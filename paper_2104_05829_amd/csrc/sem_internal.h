@@ -30,8 +30,6 @@ void set_error(const char *fmt, ...);
     } while (0)
 
 constexpr int kMaxN = 15;
-// flag bit of a chunk lane's copy index: the copy starts a segment
-constexpr int32_t kGsSegStart = 1 << 30;
 // largest Gauss rule of the dealiased advection operator (M^2 threads per element)
 constexpr int kMaxGauss = 16;
 // largest number of workgroups per CU of the persistent element-operator grid
@@ -121,7 +119,6 @@ struct Level {
     // wavefront chunks of whole segments for the gather-scatter kernel
     int64_t nchunks = 0, nover = 0;
     int32_t *chunk_b = nullptr, *chunk_e = nullptr;  // perm range of each chunk
-    int32_t *chunk_perm = nullptr;  // [nchunks][64] perm slice per lane (| kGsSegStart at segment starts), -1 past the end
     uint64_t *chunk_mask = nullptr;                   // segment-start lanes
     int32_t *over = nullptr;                          // segments longer than 64 copies
     double *D = nullptr;   // Dh [nq][nq] (row = point)
@@ -189,6 +186,17 @@ struct Workspace {
     int64_t sz_U_len = 0;
     float *sz_acc[kMaxLevels] = {};
     int sz_nv = 0;
+    // captured V-cycles, one per live right-hand-side set, each with a hash
+    // of every pointer and value its kernels take; captured on `cap`
+    struct VGraph {
+        hipGraphExec_t exec = nullptr;
+        uint32_t pack = 0;
+        int n = 0;
+        uint64_t sig = 0;
+    } vg[8];
+    int vg_next = 0;
+    bool vg_broken = false;  // capture failed once: launch kernel by kernel
+    hipStream_t cap = nullptr;
 };
 
 struct PrecondKey {

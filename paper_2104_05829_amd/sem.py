@@ -51,7 +51,7 @@ class SemSolveOpts(ctypes.Structure):
                 ("lanczos_steps", ctypes.c_int), ("cheb_lo", ctypes.c_double),
                 ("cheb_hi", ctypes.c_double), ("coarse_tol", ctypes.c_double),
                 ("coarse_maxit", ctypes.c_int), ("zero_guess", ctypes.c_int),
-                ("proj_dim", ctypes.c_int), ("smoother", ctypes.c_int)]
+                ("proj_dim", ctypes.c_int), ("smoother", ctypes.c_int), ("use_graphs", ctypes.c_int)]
 
 
 class SemSolveStats(ctypes.Structure):

@@ -125,3 +125,4 @@ def test_default_solver_options():
         (1.0, 0.0, 1e-8, 1000, S.SEM_PRECOND_JACOBI, 2, 20)
     assert (o.coarse_tol, o.coarse_maxit) == (1e-2, 20)
     assert (o.cheb_lo, o.cheb_hi, o.zero_guess, o.proj_dim) == (0.1, 1.1, 1, 0)
+    assert (o.smoother, o.use_graphs) == (S.SEM_SMOOTH_JACOBI, 0)

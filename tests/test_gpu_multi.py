@@ -244,3 +244,47 @@ def test_c3_full_size_three_rhs_pmg():
         assert rel <= 1.5e-8, (r, rel)
         assert abs(rel - sts[r]["true_rel_res"]) <= 1e-3 * rel + 1e-12
     s.free()
+
+
+@pytest.mark.skip(reason="V-cycle graph replay is switched off: in one full GPU run this test "
+                         "found a replayed solve that differed from the kernel-by-kernel solve "
+                         "(it passed when run alone); no cause was found in the library")
+@pytest.mark.parametrize("smoother", ["jacobi", "asm"])
+def test_graph_replay_matches_kernel_by_kernel(smoother):
+    """The V-cycle replayed from captured graphs gives the same iterates as
+    the kernels launched one by one: repeated single and lockstep solves
+    (the graphs replayed many times, with eager solves, host reads and
+    synchronisations between them) return bit-identical solutions and the
+    same iteration counts; a change of h2 recaptures."""
+    print(f"[gpu] graph replay {smoother}", flush=True)
+    N = 5
+    m = _mesh((3, 3, 3), N, deform="cyclic")
+    s = Sem(m, levels=(5, 3, 1))
+    B = torch.stack([s.rhs(_dev(inputs.gaussian_per_node(m.gid, 70 + r))) for r in range(3)])
+    for h2 in (2.0, 2.0, 7.0):
+        kw = dict(tol=1e-9, h1=1.0, h2=h2, precond="pmg", smoother=smoother, cheb_lo=0.25)
+        xe, ste, rce = s.solve(B[0].clone(), use_graphs=0, **kw)
+        for rep in range(3):
+            xg, stg, rcg = s.solve(B[0].clone(), use_graphs=1, **kw)
+            assert rcg == rce == 0 and stg["iters"] == ste["iters"], (rep, stg, ste)
+            assert torch.equal(xg, xe), rep
+            torch.cuda.synchronize()
+        Xe, stse, _ = s.solve_multi(B.clone(), use_graphs=0, **kw)
+        for rep in range(2):
+            Xg, stsg, _ = s.solve_multi(B.clone(), use_graphs=1, **kw)
+            assert [a["iters"] for a in stsg] == [a["iters"] for a in stse], rep
+            assert torch.equal(Xg, Xe), rep
+    s.free()
+
+
+def test_graph_replay_is_rejected():
+    """The switched-off graph path reports an error instead of running."""
+    print("[gpu] graph replay rejected", flush=True)
+    m = _mesh((2, 2, 2), 3, deform="cyclic")
+    s = Sem(m, levels=(3, 1))
+    b = s.rhs(_dev(inputs.gaussian_per_node(m.gid, 5)))
+    with pytest.raises(SemError):
+        s.solve(b, precond="pmg", use_graphs=1)
+    x, st, rc = s.solve(b, precond="pmg", use_graphs=0)
+    assert rc == 0 and st["converged"]
+    s.free()
