@@ -163,3 +163,25 @@ def test_error_paths():
     with pytest.raises(SemError):
         s9.advect_setup()  # no kernel above N = 7
     s9.free()
+
+
+def test_zero_velocity_and_single_element():
+    """A zero velocity advects nothing (output exactly 0); a single-element
+    mesh (every face a boundary) against the oracle."""
+    print("[gpu] advect zero velocity, one element", flush=True)
+    N, M = 6, 10
+    m = _mesh((1, 1, 1), N, deform="cyclic", amp=0.04, bc="neumann")
+    s = Sem(m)
+    s.advect_setup(M)
+    zero = torch.zeros((3, m.n_local), dtype=torch.float64, device="cuda")
+    ct0 = s.advect_velocity(zero)
+    c, W = _fields(m, 2, 13)
+    out0 = _host(s.advect(ct0, torch.tensor(W, device="cuda")))
+    assert np.all(out0 == 0.0)
+    ct = s.advect_velocity(torch.tensor(c, device="cuda"))
+    out = _host(s.advect(ct, torch.tensor(W, device="cuda")))
+    ct_ref = adv.conv_velocity(N, M, m.x, m.y, m.z, list(c)).reshape(m.E, 3, -1)
+    for f in range(2):
+        ref = adv.advect(N, M, ct_ref, W[f])
+        assert np.max(np.abs(out[f] - ref)) <= TOL * np.max(np.abs(ref)), f
+    s.free()
