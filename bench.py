@@ -197,6 +197,38 @@ def bench_pcg(args, torch, sem_mod, inputs):
                          "true_rel_res": [float(f"{st['true_rel_res']:.3e}") for st in sts],
                          "status": rc, "first_call_s": round(t_setup, 3)}
             del X
+        # one level-0 ASM application (FDM solves, extension combine, QQ^T,
+        # weight) on one FP32 field, HIP events; the oracle's Schwarz operator
+        # on the 5x5x5 block at the mesh corner, one thread, scaled per element
+        r32 = Bt[0].float()
+        z32 = s.smoother_apply(0, r32, smoother="asm", h1=1.0, h2=10.0)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            s.smoother_apply(0, r32, z32, smoother="asm", h1=1.0, h2=10.0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        schw["apply"] = {"call": "sem_smoother_apply level 0 (N=7), ASM, one FP32 field",
+                         "ms": round(e0.elapsed_time(e1) / 10, 4)}
+        if not args.no_cpu:
+            from threadpoolctl import threadpool_limits
+            from oracle import asm as oasm, solvers as osol
+            nqq = N + 1
+            idx = np.array([ex + ne * (ey + ne * ez) for ez in range(5) for ey in range(5) for ex in range(5)])
+            sub = inputs.BoxMesh(N=N, shape=(5, 5, 5), x=mesh.x[idx], y=mesh.y[idx], z=mesh.z[idx],
+                                 gid=mesh.gid[idx], dirichlet=mesh.dirichlet[idx])
+            with threadpool_limits(limits=1):
+                lv = osol.Level(N, sub.x, sub.y, sub.z, sub.gid, sub.dirichlet, 1.0, 10.0)
+                O = oasm.Schwarz(lv, sub.shape, sub.x, sub.y, sub.z, sub.dirichlet, "asm")
+                rs = r32.cpu().numpy().reshape(-1, nqq ** 3)[idx].reshape(-1).astype(np.float64)
+                t0 = time.perf_counter()
+                O.apply(rs)
+                dt = time.perf_counter() - t0
+            schw["apply"]["cpu_oracle"] = {"kind": "oracle", "cores": 1,
+                                           "sample": "the 5x5x5 corner block (125 elements), numpy one thread, "
+                                                     "scaled per element",
+                                           "ms_scaled": round(dt * 1e3 * mesh.E / 125, 1)}
     # difference between the two solutions (W-weighted, relative)
     diffs = []
     for a, bb in zip(res.get("pmg", []), res.get("jacobi", [])):
@@ -222,6 +254,8 @@ def bench_pcg(args, torch, sem_mod, inputs):
     for pre, v in lock.items():
         out[pre + "_lockstep"] = v
         v["speedup_vs_independent"] = round(out[pre]["ms_total"] / v["ms_total"], 3)
+    if "apply" in schw:
+        out["schwarz_apply"] = schw.pop("apply")
     for smo, v in schw.items():
         v["smoother"] = f"Chebyshev-accelerated {smo.upper()} (FDM local solves), interval [0.25, 1.1] lambda_max"
         if "pmg_lockstep" in out:
@@ -314,7 +348,26 @@ def bench_advect(args, torch, sem_mod, inputs):
     s.free()
     gbs = nbytes / (ms * 1e-3) / 1e9
     tfs = flops / (ms * 1e-3) / 1e12
-    return {"workload": f"{ne}x{ne}x{ne} deformed box, N=7, Gauss rule M={M} per direction "
+    cpu = None
+    if not args.no_cpu:
+        # the oracle on the first 256 elements, one thread: velocity transform
+        # and the three fields, scaled to the whole mesh
+        from threadpoolctl import threadpool_limits
+        from oracle import advect as oadv
+        ns = 256
+        sl = slice(0, ns * nq ** 3)
+        sub = [a.reshape(-1)[sl] for a in (mesh.x, mesh.y, mesh.z)]
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            ctr = oadv.conv_velocity(N, M, *sub, [cd[sl] for cd in c])
+            t1 = time.perf_counter()
+            for f in range(3):
+                oadv.advect(N, M, ctr, c[f][sl])
+            t2 = time.perf_counter()
+        cpu = {"kind": "oracle", "cores": 1, "sample": f"first {ns} elements, numpy one thread, scaled by {E // ns}",
+               "ms_advect_3_fields_scaled": round((t2 - t1) * 1e3 * E / ns, 1),
+               "ms_velocity_transform_scaled": round((t1 - t0) * 1e3 * E / ns, 1)}
+    return {"cpu_oracle": cpu, "workload": f"{ne}x{ne}x{ne} deformed box, N=7, Gauss rule M={M} per direction "
                         "(exact for degree 3N), the 3 velocity components advected by the velocity "
                         "(Taylor-Green-type vortex), one sem_advect call",
             "E": E, "M": M, "ms_advect_3_fields": round(ms, 4), "ms_velocity_transform": round(ms_vel, 4),
