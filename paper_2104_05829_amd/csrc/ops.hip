@@ -55,16 +55,21 @@ gs_chunk_kernel(int64_t nchunks, const int32_t *__restrict__ cb, const int32_t *
     int maxlen = len;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o));
-#pragma unroll 1
-    for (int q = 0; q < na; ++q) {
-        T *vq = v + (int64_t)((pack >> (8 * q)) & 255u) * ld;
-        const T val = act ? vq[idx] : T(0);
+    // the gathers of every live vector are issued before the first sum so
+    // their latencies overlap; each vector's sum is the same as alone
+    T val[kMaxRhs];
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q)
+        val[q] = (q < na && act) ? v[(int64_t)((pack >> (8 * q)) & 255u) * ld + idx] : T(0);
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q) {
+        if (q >= na) break;
         T acc = T(0);
         for (int j = 0; j < maxlen; ++j) {  // wave-uniform trip count
-            const T other = __shfl(val, min(s0 + j, 63));
+            const T other = __shfl(val[q], min(s0 + j, 63));
             if (j < len) acc += other;
         }
-        if (act) vq[idx] = acc;
+        if (act) v[(int64_t)((pack >> (8 * q)) & 255u) * ld + idx] = acc;
     }
 }
 
