@@ -375,7 +375,9 @@ SEM_API int sem_gll(int N, double *xi, double *rho, double *D);
  *   (M = 0: the smallest rule exact for degree 3N, M = ceil((3N+1)/2)); M must
  *   be N+1..16 and, for the compiled kernels, one of the two rules
  *   ceil((3N+1)/2) or ceil((3N+1)/2) + 1, with N <= 7; *M_used (nullable)
- *   receives M.  Device memory 72 M^3 bytes per element (freed by sem_free or
+ *   receives M.  variant picks the element kernel (the 2D and 3D thread blocks
+ *   of Sec. 3.3, enum sem_advect_variant); both give the same result up to
+ *   rounding order.  Device memory 72 M^3 bytes per element (freed by sem_free or
  *   a new setup).  Synchronises `stream`.  SEM_EMESH if det X <= 0 at a Gauss
  *   point.
  * sem_advect_velocity: ct [E][3][M^3] (point index a + M b + M^2 c, a along r)
@@ -390,7 +392,13 @@ SEM_API int sem_gll(int N, double *xi, double *rho, double *D);
  * All three are asynchronous on `stream` except the setup; errors:
  *   SEM_EINVAL (null handle or pointer, setup missing, unsupported M or nf).
  */
-SEM_API int sem_advect_setup(sem_handle h, int M, int *M_used, void *stream);
+enum sem_advect_variant {
+    SEM_ADVECT_AUTO = 0,  /* the faster of the two for (N, M) as measured on MI355X: the 2D
+                             variant at every compiled pair */
+    SEM_ADVECT_2D = 1,    /* thread per Gauss column, register arrays along the third index */
+    SEM_ADVECT_3D = 2     /* thread per Gauss point (M^3 <= 1024, so M <= 10) */
+};
+SEM_API int sem_advect_setup(sem_handle h, int M, int variant, int *M_used, void *stream);
 SEM_API int sem_advect_velocity(sem_handle h, const double *c, int64_t ldc, double *ct, void *stream);
 SEM_API int sem_advect(sem_handle h, const double *ct, int nf, const double *w, int64_t ldw,
                        double *out, int64_t ldo, void *stream);

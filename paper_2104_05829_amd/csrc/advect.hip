@@ -254,6 +254,124 @@ __global__ void __launch_bounds__((AdvShape<NQ, M>::THREADS)) __attribute__((amd
     }
 }
 
+// The 3D thread-block variant (Sec. 3.3: one thread per quadrature point,
+// possible while the M^3 points fit one workgroup, M <= 10): thread
+// t = a + M b + M^2 c owns the Gauss point (c, b, a) and keeps its three
+// contravariant velocity components in registers; every contraction is a
+// pass through LDS (three buffers used in rotation) with a barrier between.
+template <int NQ, int M>
+struct Adv3Shape {
+    static constexpr int NP = NQ * NQ * NQ, MM = M * M, M3 = MM * M;
+    static constexpr int THREADS = ((M3 + 63) / 64) * 64;
+    static constexpr int SX = (2 * NQ * NQ * M > NQ * MM) ? 2 * NQ * NQ * M : NQ * MM;  // P, Q; then G
+    static constexpr int SY = (3 * NQ * MM > NQ * NQ * M) ? 3 * NQ * MM : NQ * NQ * M;  // T; then H
+    static constexpr int SZ = (NP > M3) ? NP : M3;                                     // u; then f
+};
+
+template <int NQ, int M>
+__global__ void __launch_bounds__((Adv3Shape<NQ, M>::THREADS))
+    advect3d_kernel(int64_t E, const double *__restrict__ J, const double *__restrict__ Jd,
+                    const double *__restrict__ ct, int nf, const double *__restrict__ w, int64_t ldw,
+                    double *__restrict__ out, int64_t ldo)
+{
+    using S = Adv3Shape<NQ, M>;
+    constexpr int NP = S::NP, MM = S::MM, M3 = S::M3, TH = S::THREADS;
+    static_assert(TH <= 1024, "the 3D variant needs M^3 <= 1024");
+    __shared__ double sX[S::SX], sY[S::SY], sZ[S::SZ];
+    __shared__ double sJ[M * NQ], sJd[M * NQ];
+    const int t = threadIdx.x;
+    for (int i = t; i < M * NQ; i += TH) {
+        sJ[i] = J[i];
+        sJd[i] = Jd[i];
+    }
+    const bool pt = t < M3;
+    const int a = t % M, b = (t / M) % M, c = t / MM;
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+        if (pt) {
+            const double *cte = ct + e * 3 * M3 + t;
+            c0 = cte[0];
+            c1 = cte[M3];
+            c2 = cte[2 * M3];
+        }
+        for (int f = 0; f < nf; ++f) {
+            __syncthreads();  // the previous field's last reads are done
+            const double *u = w + f * ldw + e * NP;
+            for (int i = t; i < NP; i += TH) sZ[i] = u[i];
+            __syncthreads();
+            // over i: P[k][j][a] = J u, Q[k][j][a] = Jd u
+            if (t < NQ * NQ * M) {
+                const int a2 = t % M, j = (t / M) % NQ, k = t / (M * NQ);
+                double pp = 0.0, qq = 0.0;
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) {
+                    const double ui = sZ[(k * NQ + j) * NQ + i];
+                    pp += sJ[a2 * NQ + i] * ui;
+                    qq += sJd[a2 * NQ + i] * ui;
+                }
+                sX[(k * NQ + j) * M + a2] = pp;
+                sX[NQ * NQ * M + (k * NQ + j) * M + a2] = qq;
+            }
+            __syncthreads();
+            // over j: the three partial derivative fields T[d][k][b][a]
+            if (t < NQ * MM) {
+                const int a2 = t % M, b2 = (t / M) % M, k = t / MM;
+                double xr = 0.0, xs = 0.0, xt = 0.0;
+#pragma unroll
+                for (int j = 0; j < NQ; ++j) {
+                    const double pp = sX[(k * NQ + j) * M + a2];
+                    const double qq = sX[NQ * NQ * M + (k * NQ + j) * M + a2];
+                    xr += sJ[b2 * NQ + j] * qq;
+                    xs += sJd[b2 * NQ + j] * pp;
+                    xt += sJ[b2 * NQ + j] * pp;
+                }
+                sY[k * MM + b2 * M + a2] = xr;
+                sY[(NQ + k) * MM + b2 * M + a2] = xs;
+                sY[(2 * NQ + k) * MM + b2 * M + a2] = xt;
+            }
+            __syncthreads();
+            // over k: reference derivatives at the thread's Gauss point, integrand
+            if (pt) {
+                double dr = 0.0, ds = 0.0, dt = 0.0;
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) {
+                    dr += sJ[c * NQ + k] * sY[k * MM + b * M + a];
+                    ds += sJ[c * NQ + k] * sY[(NQ + k) * MM + b * M + a];
+                    dt += sJd[c * NQ + k] * sY[(2 * NQ + k) * MM + b * M + a];
+                }
+                sZ[t] = c0 * dr + c1 * ds + c2 * dt;
+            }
+            __syncthreads();
+            // back over c: G[k][b][a]
+            if (t < NQ * MM) {
+                const int a2 = t % M, b2 = (t / M) % M, k = t / MM;
+                double g = 0.0;
+#pragma unroll
+                for (int c2i = 0; c2i < M; ++c2i) g += sJ[c2i * NQ + k] * sZ[c2i * MM + b2 * M + a2];
+                sX[k * MM + b2 * M + a2] = g;
+            }
+            __syncthreads();
+            // back over b: H[k][j][a]
+            if (t < NQ * NQ * M) {
+                const int a2 = t % M, j = (t / M) % NQ, k = t / (M * NQ);
+                double hh = 0.0;
+#pragma unroll
+                for (int b2 = 0; b2 < M; ++b2) hh += sJ[b2 * NQ + j] * sX[k * MM + b2 * M + a2];
+                sY[(k * NQ + j) * M + a2] = hh;
+            }
+            __syncthreads();
+            // back over a: out[k][j][i]
+            if (t < NP) {
+                const int i = t % NQ, j = (t / NQ) % NQ, k = t / (NQ * NQ);
+                double o = 0.0;
+#pragma unroll
+                for (int a2 = 0; a2 < M; ++a2) o += sJ[a2 * NQ + i] * sY[(k * NQ + j) * M + a2];
+                out[f * ldo + e * NP + t] = o;
+            }
+        }
+    }
+}
+
 // Values (GRAD = false: out[e * ostride + p]) or reference gradients (GRAD:
 // out[e * ostride + q * M^3 + p], q = r, s, t) of the interpolant of the
 // L-vector u at the Gauss points p = a + M b + M^2 c.
@@ -379,6 +497,12 @@ __global__ void contra_kernel(int64_t E, int64_t M3, const double *__restrict__ 
 
 int rule_default(int N) { return (3 * N + 2) / 2; }
 
+// automatic choice: the 3D thread block up to this M, the 2D one above.  On
+// 32^3 elements, three fields, the 2D block is faster at every compiled pair
+// (N, M) = (3, 5) 75 vs 126 us, (4, 7) 170 vs 488, (5, 8) 256 vs 577,
+// (6, 10) 558 vs 1556, so the 3D block is never picked automatically.
+constexpr int kAdv3AutoMaxM = 0;
+
 bool rule_supported(int N, int M) { return N >= 1 && N <= 7 && (M == rule_default(N) || M == rule_default(N) + 1); }
 
 int64_t adv_grid(const Level &L)
@@ -413,9 +537,35 @@ int launch_fine_eval(const Level &L, int M, bool grad, const double *J, const do
     return SEM_EINVAL;
 }
 
-int launch_advect(const Level &L, int M, const double *J, const double *Jd, const double *ct, int nf,
-                  const double *w, int64_t ldw, double *out, int64_t ldo, hipStream_t s)
+#define SEM_ADV3_PAIRS(X) \
+    X(2, 2) X(2, 3) X(3, 4) X(3, 5) X(4, 5) X(4, 6) X(5, 7) X(5, 8) X(6, 8) X(6, 9) X(7, 10)
+
+bool has_3d(int nq, int M)
 {
+#define SEM_H3(NQ_, M_) \
+    if (nq == NQ_ && M == M_) return true;
+    SEM_ADV3_PAIRS(SEM_H3)
+#undef SEM_H3
+    return false;
+}
+
+int launch_advect(const Level &L, int M, int variant, const double *J, const double *Jd, const double *ct,
+                  int nf, const double *w, int64_t ldw, double *out, int64_t ldo, hipStream_t s)
+{
+    if (variant == SEM_ADVECT_3D) {
+        const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(L.E, (int64_t)(L.n_cu > 0 ? L.n_cu : 256) * 8)));
+#define SEM_ADV3(NQ_, M_)                                                                           \
+    if (L.nq == NQ_ && M == M_) {                                                                   \
+        hipLaunchKernelGGL((advect3d_kernel<NQ_, M_>), grid, dim3(Adv3Shape<NQ_, M_>::THREADS), 0, s, \
+                           L.E, J, Jd, ct, nf, w, ldw, out, ldo);                                   \
+        SEM_HIP(hipGetLastError());                                                                 \
+        return SEM_OK;                                                                              \
+    }
+        SEM_ADV3_PAIRS(SEM_ADV3)
+#undef SEM_ADV3
+        set_error("advection: no 3D kernel for N = %d, M = %d", L.N, M);
+        return SEM_EINVAL;
+    }
     // 16 workgroups per CU (measured at N = 7, M = 11: 4 per CU 712 us, 16 per
     // CU 623 us for three fields on 32^3 elements)
     const int64_t cap = (int64_t)(L.n_cu > 0 ? L.n_cu : 256) * 16;
@@ -507,7 +657,7 @@ using namespace semx;
 
 extern "C" {
 
-int sem_advect_setup(sem_handle h, int M, int *M_used, void *stream)
+int sem_advect_setup(sem_handle h, int M, int variant, int *M_used, void *stream)
 {
     if (!h || h->n_levels < 1) {
         set_error("sem_advect_setup: null handle");
@@ -524,12 +674,23 @@ int sem_advect_setup(sem_handle h, int M, int *M_used, void *stream)
         set_error("sem_advect_setup: the handle holds no coordinates");
         return SEM_EINVAL;
     }
+    if (variant != SEM_ADVECT_AUTO && variant != SEM_ADVECT_2D && variant != SEM_ADVECT_3D) {
+        set_error("sem_advect_setup: bad variant %d", variant);
+        return SEM_EINVAL;
+    }
+    const bool can3 = has_3d(N + 1, M);
+    if (variant == SEM_ADVECT_3D && !can3) {
+        set_error("sem_advect_setup: the 3D variant needs M^3 <= 1024 (M = %d, N = %d)", M, N);
+        return SEM_EINVAL;
+    }
+    if (variant == SEM_ADVECT_AUTO) variant = (can3 && M <= kAdv3AutoMaxM) ? SEM_ADVECT_3D : SEM_ADVECT_2D;
     free_advect(h);
     const int rc = advect_setup(h, M, (hipStream_t)stream);
     if (rc != SEM_OK) {
         free_advect(h);
         return rc;
     }
+    h->adv.variant = variant;
     if (M_used) *M_used = M;
     return SEM_OK;
 }
@@ -587,7 +748,7 @@ int sem_advect(sem_handle h, const double *ct, int nf, const double *w, int64_t 
         set_error("sem_advect: leading dimensions must be >= n_local = %lld", (long long)L.nL);
         return SEM_EINVAL;
     }
-    return launch_advect(L, A.M, A.J, A.Jd, ct, nf, w, ldw, out, ldo, (hipStream_t)stream);
+    return launch_advect(L, A.M, A.variant, A.J, A.Jd, ct, nf, w, ldw, out, ldo, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -221,6 +221,7 @@ struct sem_handle_s {
     // F [E][9][M^3] = rho~ |det X| dr_q/dx_d at index 3 q + d
     struct Advect {
         int M = 0;
+        int variant = 0;  // SEM_ADVECT_2D or SEM_ADVECT_3D
         double *J = nullptr, *Jd = nullptr, *wq = nullptr, *F = nullptr;
     } adv;
     semx::Workspace ws;

@@ -22,6 +22,7 @@ SEM_OK, SEM_EINVAL, SEM_ENOMEM, SEM_EHIP, SEM_ENOCONV, SEM_EBREAKDOWN, SEM_EMESH
 SEM_F64, SEM_F32 = 0, 1
 SEM_PRECOND_JACOBI, SEM_PRECOND_PMG = 0, 1
 SEM_SMOOTH_JACOBI, SEM_SMOOTH_ASM, SEM_SMOOTH_RAS = 0, 1, 2
+SEM_ADVECT_AUTO, SEM_ADVECT_2D, SEM_ADVECT_3D = 0, 1, 2
 SEM_MAX_RHS = 4
 SEM_MAX_PROJ = 16
 
@@ -99,7 +100,7 @@ _SIGS = {
                                               _VP, _VP, _VP]),
     "sem_smoother_apply": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                           ctypes.c_double, _VP, _VP, _VP]),
-    "sem_advect_setup": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _VP]),
+    "sem_advect_setup": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _VP]),
     "sem_advect_velocity": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP, _VP]),
     "sem_advect": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP, ctypes.c_int64, _VP, ctypes.c_int64, _VP]),
     "sem_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(SemSolveOpts),
@@ -448,11 +449,13 @@ class Sem:
         return z
 
     # -- dealiased advection ----------------------------------------------
-    def advect_setup(self, M=None):
+    def advect_setup(self, M=None, variant="auto"):
         """Metric factors for the M-point Gauss rule (None: the smallest rule
-        exact for degree 3N); returns M."""
+        exact for degree 3N) and the element kernel ("auto", "2d", "3d");
+        returns M."""
         m = ctypes.c_int(0)
-        _check(lib().sem_advect_setup(self._handle(), int(M or 0), ctypes.byref(m), _stream()),
+        code = {"auto": SEM_ADVECT_AUTO, "2d": SEM_ADVECT_2D, "3d": SEM_ADVECT_3D}.get(variant, variant)
+        _check(lib().sem_advect_setup(self._handle(), int(M or 0), int(code), ctypes.byref(m), _stream()),
                "sem_advect_setup")
         self.adv_m = int(m.value)
         return self.adv_m

@@ -112,7 +112,7 @@ def test_host_error_paths():
     assert L.sem_gs_level_multi(None, 0, 0, 3, None, 10, None) == S.SEM_EINVAL
     assert L.sem_pcg_solve_multi(None, 3, None, None, 10, ctypes.byref(o), None, None) == S.SEM_EINVAL
     assert L.sem_proj_reset(None) == S.SEM_EINVAL
-    assert L.sem_advect_setup(None, 0, None, None) == S.SEM_EINVAL
+    assert L.sem_advect_setup(None, 0, 0, None, None) == S.SEM_EINVAL
     assert L.sem_advect_velocity(None, None, 10, None, None) == S.SEM_EINVAL
     assert L.sem_advect(None, None, 1, None, 10, None, 10, None) == S.SEM_EINVAL
     info = S.SemInfo()

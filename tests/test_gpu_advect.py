@@ -47,12 +47,15 @@ CASES = [((3, 2, 2), 7, 11), ((2, 2, 3), 7, 12), ((3, 3, 2), 3, 5), ((2, 2, 2), 
          ((2, 2, 2), 2, 4), ((2, 2, 2), 2, 5), ((2, 2, 2), 4, 8), ((1, 2, 1), 6, 11)]
 
 
-@pytest.mark.parametrize("shape,N,M", CASES)
-def test_advect_matches_oracle(shape, N, M):
-    print(f"[gpu] advect {shape} N={N} M={M}", flush=True)
+CASES_V = [(sh, N, M, v) for sh, N, M in CASES for v in ("2d", "3d") if v == "2d" or M <= 10]
+
+
+@pytest.mark.parametrize("shape,N,M,variant", CASES_V)
+def test_advect_matches_oracle(shape, N, M, variant):
+    print(f"[gpu] advect {shape} N={N} M={M} {variant}", flush=True)
     m = _mesh(shape, N, deform="cyclic", amp=0.06, bc="neumann")
     s = Sem(m)
-    assert s.advect_setup(M) == M
+    assert s.advect_setup(M, variant=variant) == M
     c, W = _fields(m, 4, 7)
     ct = s.advect_velocity(torch.tensor(c, device="cuda"))
     ct_ref = adv.conv_velocity(N, M, m.x, m.y, m.z, list(c)).reshape(m.E, 3, -1)
@@ -152,6 +155,10 @@ def test_error_paths():
     for M in (7, 10, 13, 17):
         with pytest.raises(SemError):
             s.advect_setup(M)
+    with pytest.raises(SemError):
+        s.advect_setup(11, variant="3d")  # 11^3 points exceed one workgroup
+    with pytest.raises(SemError):
+        s.advect_setup(11, variant=7)
     M = s.advect_setup()
     ct = torch.zeros((m.E, 3, M ** 3), dtype=torch.float64, device="cuda")
     W = torch.zeros((5, m.n_local), dtype=torch.float64, device="cuda")
@@ -163,6 +170,23 @@ def test_error_paths():
     with pytest.raises(SemError):
         s9.advect_setup()  # no kernel above N = 7
     s9.free()
+
+
+@pytest.mark.parametrize("N,M", [(6, 10), (5, 8), (4, 7)])
+def test_3d_and_2d_variants_agree(N, M):
+    """The two thread-block variants on the same inputs: equal up to
+    rounding order (1e-13 of the largest output)."""
+    print(f"[gpu] advect variants N={N} M={M}", flush=True)
+    m = _mesh((4, 3, 3), N, deform="cyclic", bc="neumann")
+    c, W = _fields(m, 3, 17)
+    outs = []
+    for variant in ("2d", "3d"):
+        s = Sem(m)
+        s.advect_setup(M, variant=variant)
+        ct = s.advect_velocity(torch.tensor(c, device="cuda"))
+        outs.append(_host(s.advect(ct, torch.tensor(W, device="cuda"))))
+        s.free()
+    assert np.max(np.abs(outs[0] - outs[1])) <= 1e-13 * np.max(np.abs(outs[0]))
 
 
 def test_zero_velocity_and_single_element():
