@@ -71,7 +71,7 @@ def test_adjoint_central_differences_c4():
     1e-18 here, so ~1e-12 after dividing by h); these directions have
     directional derivatives of order 1e-5, so agreement to 1e-6 relative is
     meaningful.  Sampled single entries (the largest |dL/dk|, about 8e-7 each)
-    sit within a factor of 1e6 of that noise floor, so they are judged at
+    sit within a factor of 1e6 of that noise floor, so they are assessed at
     1e-5 of max |dL/dk|."""
     print("[gpu] adjoint FD 8^3 N=7", flush=True)
     N = 7
