@@ -19,6 +19,7 @@
 // with N >= 2), the 1D operators and their eigen-decompositions (cyclic
 // Jacobi on M^{-1/2} K M^{-1/2}), and the accumulation lists.
 #include <algorithm>
+#include <thread>
 #include <cmath>
 #include <numeric>
 #include <vector>
@@ -146,6 +147,50 @@ struct SchwarzHost {
     std::vector<float> S, lam, w;
 };
 
+// host threads for the per-element setup work (at most 16)
+static int host_threads()
+{
+    const unsigned hc = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(16u, hc));
+}
+
+// fn(lo, hi) on [0, n) split into contiguous ranges, one per thread
+template <typename Fn>
+static void parallel_ranges(int64_t n, Fn fn)
+{
+    const int nt = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(1, n / 64));
+    if (nt <= 1) {
+        fn((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int i = 0; i < nt; ++i) th.emplace_back(fn, n * i / nt, n * (i + 1) / nt);
+    for (auto &t : th) t.join();
+}
+
+// sort v (pairs, lexicographic) in threaded chunks, then merge them pairwise
+static void parallel_sort(std::vector<std::pair<int64_t, int64_t>> &v)
+{
+    const int64_t n = (int64_t)v.size();
+    const int nt = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(1, n / 4096));
+    std::vector<int64_t> cut(nt + 1);
+    for (int i = 0; i <= nt; ++i) cut[i] = n * i / nt;
+    {
+        std::vector<std::thread> th;
+        for (int i = 0; i < nt; ++i)
+            th.emplace_back([&, i] { std::sort(v.begin() + cut[i], v.begin() + cut[i + 1]); });
+        for (auto &t : th) t.join();
+    }
+    for (int width = 1; width < nt; width *= 2) {
+        std::vector<std::thread> th;
+        for (int i = 0; i + width < nt; i += 2 * width) {
+            const int64_t a = cut[i], m = cut[i + width], b = cut[std::min(i + 2 * width, nt)];
+            th.emplace_back([&v, a, m, b] { std::inplace_merge(v.begin() + a, v.begin() + m, v.begin() + b); });
+        }
+        for (auto &t : th) t.join();
+    }
+}
+
 static int schwarz_host(int N, int64_t E, const int64_t *gid, const uint8_t *dir, const double *len,
                         SchwarzHost &out)
 {
@@ -161,12 +206,15 @@ static int schwarz_host(int N, int64_t E, const int64_t *gid, const uint8_t *dir
     }
     // copies of every nonzero pointer, sorted by (pointer, copy)
     std::vector<int64_t> ord;
-    ord.reserve(nL);
-    for (int64_t l = 0; l < nL; ++l)
-        if (gid[l] != 0) ord.push_back(l);
-    std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
-        return gid[a] != gid[b] ? gid[a] < gid[b] : a < b;
-    });
+    {
+        std::vector<std::pair<int64_t, int64_t>> gl;
+        gl.reserve(nL);
+        for (int64_t l = 0; l < nL; ++l)
+            if (gid[l] != 0) gl.emplace_back(gid[l], l);
+        parallel_sort(gl);
+        ord.resize(gl.size());
+        for (size_t i = 0; i < gl.size(); ++i) ord[i] = gl[i].second;
+    }
     auto first_of = [&](int64_t g) {
         return std::lower_bound(ord.begin(), ord.end(), g, [&](int64_t l, int64_t v) { return gid[l] < v; });
     };
@@ -275,7 +323,6 @@ static int schwarz_host(int N, int64_t E, const int64_t *gid, const uint8_t *dir
     out.S.assign((size_t)E * 3 * ne * ne, 0.0f);
     out.lam.assign((size_t)E * 3 * ne, 1.0f);
     out.ix.assign((size_t)E * ne3, -1);
-    std::vector<uint8_t> keep(3 * ne);
     auto face_dirichlet = [&](int64_t e, int d, int side) {
         const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
         for (int v = 0; v < nq; ++v)
@@ -288,23 +335,27 @@ static int schwarz_host(int N, int64_t E, const int64_t *gid, const uint8_t *dir
             }
         return true;
     };
-    for (int64_t e = 0; e < E; ++e) {
-        for (int d = 0; d < 3; ++d) {
-            const FaceLink &Fl = link[e * 6 + d * 2], &Fh = link[e * 6 + d * 2 + 1];
-            const double Lm = Fl.nb >= 0 ? len[Fl.nb * 3 + Fl.rax[d]] : -1.0;
-            const double Lp = Fh.nb >= 0 ? len[Fh.nb * 3 + Fh.rax[d]] : -1.0;
-            fdm_direction(N, rho.data(), D.data(), len[e * 3 + d], Lm, Lp, face_dirichlet(e, d, 0),
-                          face_dirichlet(e, d, 1), out.S.data() + ((size_t)e * 3 + d) * ne * ne,
-                          out.lam.data() + ((size_t)e * 3 + d) * ne, keep.data() + d * ne);
+    // every element's FDM modes and extended-point map, independently
+    parallel_ranges(E, [&](int64_t e0, int64_t e1) {
+        std::vector<uint8_t> keep(3 * ne);
+        for (int64_t e = e0; e < e1; ++e) {
+            for (int d = 0; d < 3; ++d) {
+                const FaceLink &Fl = link[e * 6 + d * 2], &Fh = link[e * 6 + d * 2 + 1];
+                const double Lm = Fl.nb >= 0 ? len[Fl.nb * 3 + Fl.rax[d]] : -1.0;
+                const double Lp = Fh.nb >= 0 ? len[Fh.nb * 3 + Fh.rax[d]] : -1.0;
+                fdm_direction(N, rho.data(), D.data(), len[e * 3 + d], Lm, Lp, face_dirichlet(e, d, 0),
+                              face_dirichlet(e, d, 1), out.S.data() + ((size_t)e * 3 + d) * ne * ne,
+                              out.lam.data() + ((size_t)e * 3 + d) * ne, keep.data() + d * ne);
+            }
+            for (int c = 0; c < ne; ++c)
+                for (int b = 0; b < ne; ++b)
+                    for (int a = 0; a < ne; ++a) {
+                        if (!(keep[a] && keep[ne + b] && keep[2 * ne + c])) continue;
+                        int64_t cc[3] = {a - 1, b - 1, c - 1};
+                        out.ix[(size_t)e * ne3 + ((int64_t)c * ne + b) * ne + a] = (int32_t)walk(e, cc);
+                    }
         }
-        for (int c = 0; c < ne; ++c)
-            for (int b = 0; b < ne; ++b)
-                for (int a = 0; a < ne; ++a) {
-                    if (!(keep[a] && keep[ne + b] && keep[2 * ne + c])) continue;
-                    int64_t cc[3] = {a - 1, b - 1, c - 1};
-                    out.ix[(size_t)e * ne3 + ((int64_t)c * ne + b) * ne + a] = (int32_t)walk(e, cc);
-                }
-    }
+    });
     // accumulation lists: the local-solution entries landing on every copy, ascending
     out.off.assign(nL + 1, 0);
     for (int64_t t = 0; t < E * ne3; ++t)
@@ -349,28 +400,36 @@ int build_schwarz(Level &L, hipStream_t s)
     const int next = ne * ne * ne - nq * nq * nq;
     const int64_t E = L.E, ne3 = (int64_t)ne * ne * ne;
     std::vector<int32_t> hx((size_t)E * next, -1);
-    std::vector<std::pair<int32_t, int32_t>> contrib;  // (copy, extension entry)
-    for (int64_t e = 0; e < E; ++e)
-        for (int c = 0; c < ne; ++c)
-            for (int b = 0; b < ne; ++b)
-                for (int a = 0; a < ne; ++a) {
-                    const bool inner = a > 0 && a < ne - 1 && b > 0 && b < ne - 1 && c > 0 && c < ne - 1;
-                    if (inner) continue;
-                    const int32_t q = H.ix[(size_t)e * ne3 + ((int64_t)c * ne + b) * ne + a];
-                    const int64_t slot = e * next + schwarz_ext_slot(ne, a, b, c);
-                    hx[slot] = q;
-                    if (q >= 0) contrib.emplace_back(q, (int32_t)slot);
-                }
-    std::sort(contrib.begin(), contrib.end());
+    parallel_ranges(E, [&](int64_t e0, int64_t e1) {
+        for (int64_t e = e0; e < e1; ++e)
+            for (int c = 0; c < ne; ++c)
+                for (int b = 0; b < ne; ++b)
+                    for (int a = 0; a < ne; ++a) {
+                        const bool inner = a > 0 && a < ne - 1 && b > 0 && b < ne - 1 && c > 0 && c < ne - 1;
+                        if (inner) continue;
+                        hx[e * next + schwarz_ext_slot(ne, a, b, c)] =
+                            H.ix[(size_t)e * ne3 + ((int64_t)c * ne + b) * ne + a];
+                    }
+    });
+    // copies receiving extension values (ascending) and, per copy, its
+    // extension entries in ascending slot order: a counting pass over slots
+    std::vector<int32_t> cnt(L.nL + 1, 0);
+    for (int64_t slot = 0; slot < E * next; ++slot)
+        if (hx[slot] >= 0) ++cnt[hx[slot] + 1];
     std::vector<int32_t> rc, off, src;
-    for (size_t i = 0; i < contrib.size();) {
-        size_t j = i;
-        rc.push_back(contrib[i].first);
-        off.push_back((int32_t)src.size());
-        while (j < contrib.size() && contrib[j].first == contrib[i].first) src.push_back(contrib[j++].second);
-        i = j;
-    }
-    off.push_back((int32_t)src.size());
+    std::vector<int32_t> pos(L.nL, -1);  // first list position of each receiving copy
+    int64_t total = 0;
+    for (int64_t q = 0; q < L.nL; ++q)
+        if (cnt[q + 1] > 0) {
+            rc.push_back((int32_t)q);
+            off.push_back((int32_t)total);
+            pos[q] = (int32_t)total;
+            total += cnt[q + 1];
+        }
+    off.push_back((int32_t)total);
+    src.assign(total, 0);
+    for (int64_t slot = 0; slot < E * next; ++slot)
+        if (hx[slot] >= 0) src[pos[hx[slot]]++] = (int32_t)slot;
     auto up = [&](void **dst, const void *src_, size_t bytes) -> int {
         SEM_HIP(hipMalloc(dst, bytes > 0 ? bytes : 4));
         if (bytes) SEM_HIP(hipMemcpyAsync(*dst, src_, bytes, hipMemcpyHostToDevice, s));
