@@ -143,7 +143,7 @@ void free_schwarz(Level &L)
 // Host setup of one level: gather map ix [E][ne^3], FDM data S [E][3][ne][ne]
 // and lam [E][3][ne], accumulation lists off [nL+1] / src, weight w [nL].
 struct SchwarzHost {
-    std::vector<int32_t> ix, off, src;
+    std::vector<int32_t> ix, off;
     std::vector<float> S, lam, w;
 };
 
@@ -356,15 +356,12 @@ static int schwarz_host(int N, int64_t E, const int64_t *gid, const uint8_t *dir
                     }
         }
     });
-    // accumulation lists: the local-solution entries landing on every copy, ascending
+    // offsets of the local-solution entries landing on every copy (only the
+    // counts, off[l + 1] - off[l], are used)
     out.off.assign(nL + 1, 0);
     for (int64_t t = 0; t < E * ne3; ++t)
         if (out.ix[t] >= 0) ++out.off[out.ix[t] + 1];
     std::partial_sum(out.off.begin(), out.off.end(), out.off.begin());
-    out.src.assign(out.off[nL], 0);
-    std::vector<int32_t> fill(out.off.begin(), out.off.end() - 1);
-    for (int64_t t = 0; t < E * ne3; ++t)
-        if (out.ix[t] >= 0) out.src[fill[out.ix[t]]++] = (int32_t)t;
     // weight: mask / (subdomains containing the node), summed over its copies
     std::vector<double> node_cov(nL);
     for (int64_t l = 0; l < nL; ++l) node_cov[l] = out.off[l + 1] - out.off[l];
