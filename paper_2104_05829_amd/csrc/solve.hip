@@ -28,48 +28,85 @@ static int red_grid(int64_t n)
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb, kMaxRedBlocks));
 }
 
-// deterministic block sum of NV values per thread; thread v < NV writes
-// out[blockIdx.x * NV + v]
+// Fixed-order tree over the kRB per-thread values acc[q] of a block: pairs
+// (t, t + st) for st = kRB / 2, ..., 1, the steps down to 64 through LDS and
+// the last six inside wavefront 0 by lane shuffles (same pairs, no barriers).
+// The block's sums end in thread 0's acc.
+template <int NV>
+__device__ inline void block_tree(double (&sh)[NV][kRB], double (&acc)[NV])
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) sh[q][t] = acc[q];
+    __syncthreads();
+#pragma unroll
+    for (int st = kRB / 2; st >= 64; st >>= 1) {
+        if (t < st)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) sh[q][t] += sh[q][t + st];
+        __syncthreads();
+    }
+    if (t < 64) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) acc[q] = sh[q][t];
+#pragma unroll
+        for (int st = 32; st >= 1; st >>= 1)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) acc[q] += __shfl_down(acc[q], st, 64);
+    }
+}
+
+// deterministic block sum of NV values per thread; thread 0 writes
+// out[blockIdx.x * NV + q] for q < NV
 template <int NV>
 __device__ inline void block_sum_store(const double (&v)[NV], double *out)
 {
     __shared__ double sh[NV][kRB];
-    const int t = threadIdx.x;
+    double acc[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) sh[q][t] = v[q];
-    __syncthreads();
-    for (int st = kRB / 2; st > 0; st >>= 1) {
-        if (t < st)
+    for (int q = 0; q < NV; ++q) acc[q] = v[q];
+    block_tree<NV>(sh, acc);
+    if (threadIdx.x == 0)
 #pragma unroll
-            for (int q = 0; q < NV; ++q) sh[q][t] += sh[q][t + st];
-        __syncthreads();
-    }
-    if (t < NV) out[(int64_t)blockIdx.x * NV + t] = sh[t][0];
+        for (int q = 0; q < NV; ++q) out[(int64_t)blockIdx.x * NV + q] = acc[q];
 }
 
-// deterministic sum of nb partial records of NV values (one block of kRB)
+// deterministic sum of nb partial records of NV values (one block of kRB),
+// returned to every thread.  Thread t adds records t, t + kRB, ... in order;
+// the loads of kPartUnroll consecutive records are issued before their adds,
+// so a long partial list costs few memory round trips.
+constexpr int kPartUnroll = 8;
 template <int NV>
 __device__ inline void sum_partials(const double *partial, int64_t nb, double (&res)[NV])
 {
     __shared__ double sh[NV][kRB];
+    __shared__ double bc[NV];
     const int t = threadIdx.x;
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-    for (int64_t b = t; b < nb; b += kRB)
+    int64_t b = t;
+    for (; b + (kPartUnroll - 1) * kRB < nb; b += kPartUnroll * kRB) {
+        double v[kPartUnroll][NV];
+#pragma unroll
+        for (int u = 0; u < kPartUnroll; ++u)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[u][q] = partial[(b + u * kRB) * NV + q];
+#pragma unroll
+        for (int u = 0; u < kPartUnroll; ++u)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) acc[q] += v[u][q];
+    }
+    for (; b < nb; b += kRB)
 #pragma unroll
         for (int q = 0; q < NV; ++q) acc[q] += partial[b * NV + q];
+    block_tree<NV>(sh, acc);
+    if (t == 0)
 #pragma unroll
-    for (int q = 0; q < NV; ++q) sh[q][t] = acc[q];
+        for (int q = 0; q < NV; ++q) bc[q] = acc[q];
     __syncthreads();
-    for (int st = kRB / 2; st > 0; st >>= 1) {
-        if (t < st)
 #pragma unroll
-            for (int q = 0; q < NV; ++q) sh[q][t] += sh[q][t + st];
-        __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < NV; ++q) res[q] = sh[q][0];
+    for (int q = 0; q < NV; ++q) res[q] = bc[q];
 }
 
 // ------------------------------------------------------------------ vectors
