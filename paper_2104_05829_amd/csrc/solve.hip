@@ -12,6 +12,7 @@
 // without a host round trip per iteration.
 #include <algorithm>
 #include <chrono>
+#include <initializer_list>
 #include <cmath>
 #include <vector>
 
@@ -26,6 +27,16 @@ static int red_grid(int64_t n)
 {
     const int64_t nb = (n + kRB - 1) / kRB;
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb, kMaxRedBlocks));
+}
+
+// float4 access is possible: n and ld multiples of 4, every array (null
+// entries ignored) 16-byte aligned
+static bool vec4_ok(int64_t n, int64_t ld, std::initializer_list<const void *> ptrs)
+{
+    if ((n | ld) & 3) return false;
+    for (const void *p : ptrs)
+        if (p && (reinterpret_cast<uintptr_t>(p) & 15)) return false;
+    return true;
 }
 
 // Fixed-order tree over the kRB per-thread values acc[q] of a block: pairs
@@ -107,6 +118,35 @@ __device__ inline void sum_partials(const double *partial, int64_t nb, double (&
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NV; ++q) res[q] = bc[q];
+}
+
+// four consecutive values g*4 .. g*4+3 as 16-byte accesses (arrays 16-byte
+// aligned, checked by the launching code)
+__device__ inline void ld4(const double *p, int64_t g, double (&o)[4])
+{
+    const double2 a = reinterpret_cast<const double2 *>(p)[2 * g];
+    const double2 b = reinterpret_cast<const double2 *>(p)[2 * g + 1];
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = b.x;
+    o[3] = b.y;
+}
+__device__ inline void st4(double *p, int64_t g, const double (&o)[4])
+{
+    reinterpret_cast<double2 *>(p)[2 * g] = make_double2(o[0], o[1]);
+    reinterpret_cast<double2 *>(p)[2 * g + 1] = make_double2(o[2], o[3]);
+}
+__device__ inline void ld4(const float *p, int64_t g, float (&o)[4])
+{
+    const float4 a = reinterpret_cast<const float4 *>(p)[g];
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = a.z;
+    o[3] = a.w;
+}
+__device__ inline void st4(float *p, int64_t g, const float (&o)[4])
+{
+    reinterpret_cast<float4 *>(p)[g] = make_float4(o[0], o[1], o[2], o[3]);
 }
 
 // ------------------------------------------------------------------ vectors
@@ -234,6 +274,7 @@ __global__ void fin_init_kernel(VSet vs, const double *partial, int64_t pst, int
 // (p, A_L p) in the same fixed order, so all blocks hold the same alpha;
 // x += alpha p; r -= alpha QQ^T(A_L p) (w already assembled); partials
 // (W r Dinv r, W r r).  rz2[parity] is the current (r, z).
+template <bool V4>
 __global__ void pcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t ldx,
                                         KrylovScalars *sc, int parity,
                                         const double *__restrict__ pax, int64_t pst_ax, int64_t nbax,
@@ -267,13 +308,36 @@ __global__ void pcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t 
         sc->alpha = a;
     }
     double s[2] = {0.0, 0.0};
-    GRID_LOOP(i, n) {
-        x[i] += a * p[i];
-        const double ri = r[i] - a * w[i];
-        r[i] = ri;
-        const double wr = W[i] * ri;
-        s[0] += wr * Dinv[i] * ri;
-        s[1] += wr * ri;
+    if constexpr (V4) {
+        GRID_LOOP(g, n >> 2) {
+            double pp[4], ww[4], xx[4], rr[4], wt[4], dd[4];
+            ld4(p, g, pp);
+            ld4(w, g, ww);
+            ld4(x, g, xx);
+            ld4(r, g, rr);
+            ld4(W, g, wt);
+            ld4(Dinv, g, dd);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                xx[k] += a * pp[k];
+                const double ri = rr[k] - a * ww[k];
+                rr[k] = ri;
+                const double wr = wt[k] * ri;
+                s[0] += wr * dd[k] * ri;
+                s[1] += wr * ri;
+            }
+            st4(x, g, xx);
+            st4(r, g, rr);
+        }
+    } else {
+        GRID_LOOP(i, n) {
+            x[i] += a * p[i];
+            const double ri = r[i] - a * w[i];
+            r[i] = ri;
+            const double wr = W[i] * ri;
+            s[0] += wr * Dinv[i] * ri;
+            s[1] += wr * ri;
+        }
     }
     block_sum_store<2>(s, partial + v * pst);
 }
@@ -281,6 +345,7 @@ __global__ void pcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t 
 // Jacobi-PCG direction update with beta and the convergence decision taken
 // by every block from the update's partials (identical in all blocks);
 // block 0 records them.  `iter` is the 1-based number of this iteration.
+template <bool V4>
 __global__ void pcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars *sc, int parity,
                                    int iter, const double *__restrict__ pu, int64_t pst, int64_t nbu,
                                    const double *__restrict__ Dinv, const double *__restrict__ r,
@@ -306,12 +371,25 @@ __global__ void pcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars
     }
     if (stop) return;
     const double be = rz / sc->rz2[parity];
-    GRID_LOOP(i, n) p[i] = Dinv[i] * r[i] + be * p[i];
+    if constexpr (V4) {
+        GRID_LOOP(g, n >> 2) {
+            double dd[4], rr[4], pp[4];
+            ld4(Dinv, g, dd);
+            ld4(r, g, rr);
+            ld4(p, g, pp);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pp[k] = dd[k] * rr[k] + be * pp[k];
+            st4(p, g, pp);
+        }
+    } else {
+        GRID_LOOP(i, n) p[i] = Dinv[i] * r[i] + be * p[i];
+    }
 }
 
 // flexible-CG update: alpha from the operator partials, x += alpha p,
 // r -= alpha QQ^T(A_L p), r32 = FP32 copy of r (the V-cycle input);
 // partial (W r r)
+template <bool V4>
 __global__ void fcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t ldx,
                                         KrylovScalars *sc, int parity,
                                         const double *__restrict__ pax, int64_t pst_ax, int64_t nbax,
@@ -345,18 +423,42 @@ __global__ void fcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t 
         sc->alpha = a;
     }
     double s[1] = {0.0};
-    GRID_LOOP(i, n) {
-        x[i] += a * p[i];
-        const double ri = r[i] - a * w[i];
-        r[i] = ri;
-        r32[i] = (float)ri;
-        s[0] += W[i] * ri * ri;
+    if constexpr (V4) {
+        GRID_LOOP(g, n >> 2) {
+            double pp[4], ww[4], xx[4], rr[4], wt[4];
+            float rf[4];
+            ld4(p, g, pp);
+            ld4(w, g, ww);
+            ld4(x, g, xx);
+            ld4(r, g, rr);
+            ld4(W, g, wt);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                xx[k] += a * pp[k];
+                const double ri = rr[k] - a * ww[k];
+                rr[k] = ri;
+                rf[k] = (float)ri;
+                s[0] += wt[k] * ri * ri;
+            }
+            st4(x, g, xx);
+            st4(r, g, rr);
+            st4(r32, g, rf);
+        }
+    } else {
+        GRID_LOOP(i, n) {
+            x[i] += a * p[i];
+            const double ri = r[i] - a * w[i];
+            r[i] = ri;
+            r32[i] = (float)ri;
+            s[0] += W[i] * ri * ri;
+        }
     }
     block_sum_store<1>(s, partial + v * pst);
 }
 
 // (z, w)_W and (z, r)_W for assembled w, z the FP32 V-cycle output taken to
 // FP64 (W = 0 on Dirichlet copies applies the restriction)
+template <bool V4>
 __global__ void dot_zw_kernel(int64_t n, VSet vs, int64_t ld, const KrylovScalars *sc,
                               const double *__restrict__ W, const float *__restrict__ z,
                               const double *__restrict__ wa, const double *__restrict__ r,
@@ -368,10 +470,27 @@ __global__ void dot_zw_kernel(int64_t n, VSet vs, int64_t ld, const KrylovScalar
     wa += v * ld;
     r += v * ld;
     double s[2] = {0.0, 0.0};
-    GRID_LOOP(i, n) {
-        const double wz = W[i] * (double)z[i];
-        s[0] += wz * wa[i];
-        s[1] += wz * r[i];
+    if constexpr (V4) {
+        GRID_LOOP(g, n >> 2) {
+            double wt[4], ww[4], rr[4];
+            float zz[4];
+            ld4(W, g, wt);
+            ld4(z, g, zz);
+            ld4(wa, g, ww);
+            ld4(r, g, rr);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double wz = wt[k] * (double)zz[k];
+                s[0] += wz * ww[k];
+                s[1] += wz * rr[k];
+            }
+        }
+    } else {
+        GRID_LOOP(i, n) {
+            const double wz = W[i] * (double)z[i];
+            s[0] += wz * wa[i];
+            s[1] += wz * r[i];
+        }
     }
     block_sum_store<2>(s, partial + v * pst);
 }
@@ -380,6 +499,7 @@ __global__ void dot_zw_kernel(int64_t n, VSet vs, int64_t ld, const KrylovScalar
 // = -alpha (z_new, A p) / rz_old (r_new - r_old = -alpha A p), taken by every
 // block from the partials of dot_zw_kernel; first = 1 gives p = z.  z is the
 // FP32 V-cycle output, zero on Dirichlet copies (mask W32 > 0).
+template <bool V4>
 __global__ void fcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars *sc, int parity,
                                    const double *__restrict__ pz, int64_t pst, int64_t nbz,
                                    const float *__restrict__ z, const float *__restrict__ W32,
@@ -406,11 +526,40 @@ __global__ void fcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars
         }
     }
     if (bad) return;
-    GRID_LOOP(i, n) p[i] = (W32[i] > 0.0f ? (double)z[i] : 0.0) + be * p[i];
+    if constexpr (V4) {
+        GRID_LOOP(g, n >> 2) {
+            float zz[4], wt[4];
+            double pp[4];
+            ld4(z, g, zz);
+            ld4(W32, g, wt);
+            ld4(p, g, pp);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pp[k] = (wt[k] > 0.0f ? (double)zz[k] : 0.0) + be * pp[k];
+            st4(p, g, pp);
+        }
+    } else {
+        GRID_LOOP(i, n) p[i] = (W32[i] > 0.0f ? (double)z[i] : 0.0) + be * p[i];
+    }
 }
 
 // Chebyshev step on assembled t = QQ^T A_L x (t null when x = 0):
 // res = r - t, d = c1 d + c2 Dinv res, x += d (x = d when `init`)
+// One Chebyshev-Jacobi point update (res = r - t, or r when t is absent).
+__device__ inline void cheb_pt(float r, float t, bool has_t, float dinv, float &d, float &x,
+                               float c1, float c2, int init)
+{
+    const float res = has_t ? r - t : r;
+    const float di = (init ? 0.0f : c1 * d) + c2 * dinv * res;
+    d = di;
+    x = init ? di : x + di;
+}
+
+// FP32 streaming kernels take 16 bytes per lane (float4) when V4: n and ld
+// multiples of 4 and every array 16-byte aligned (checked by the caller); the
+// arithmetic per point is the same as in the one-float form.
+#define FLOAT4_AT(p, i) (reinterpret_cast<const float4 *>(p)[i])
+
+template <bool V4>
 __global__ void cheb_fused_kernel(int64_t n, VSet vs, int64_t ld, const float *__restrict__ r,
                                   const float *__restrict__ t, const float *__restrict__ Dinv,
                                   float *__restrict__ d, float *__restrict__ x, float c1, float c2,
@@ -421,16 +570,36 @@ __global__ void cheb_fused_kernel(int64_t n, VSet vs, int64_t ld, const float *_
     if (t) t += v * ld;
     d += v * ld;
     x += v * ld;
-    GRID_LOOP(i, n) {
-        const float res = t ? r[i] - t[i] : r[i];
-        const float di = (init ? 0.0f : c1 * d[i]) + c2 * Dinv[i] * res;
-        d[i] = di;
-        x[i] = init ? di : x[i] + di;
+    const bool ht = t != nullptr;
+    if constexpr (V4) {
+        GRID_LOOP(i, n >> 2) {
+            const float4 rv = FLOAT4_AT(r, i), gv = FLOAT4_AT(Dinv, i);
+            const float4 tv = ht ? FLOAT4_AT(t, i) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            float4 dv = make_float4(0.0f, 0.0f, 0.0f, 0.0f), xv = dv;
+            if (!init) {
+                dv = FLOAT4_AT(d, i);
+                xv = FLOAT4_AT(x, i);
+            }
+            cheb_pt(rv.x, tv.x, ht, gv.x, dv.x, xv.x, c1, c2, init);
+            cheb_pt(rv.y, tv.y, ht, gv.y, dv.y, xv.y, c1, c2, init);
+            cheb_pt(rv.z, tv.z, ht, gv.z, dv.z, xv.z, c1, c2, init);
+            cheb_pt(rv.w, tv.w, ht, gv.w, dv.w, xv.w, c1, c2, init);
+            reinterpret_cast<float4 *>(d)[i] = dv;
+            reinterpret_cast<float4 *>(x)[i] = xv;
+        }
+    } else {
+        GRID_LOOP(i, n) {
+            float di = init ? 0.0f : d[i], xi = init ? 0.0f : x[i];
+            cheb_pt(r[i], ht ? t[i] : 0.0f, ht, Dinv[i], di, xi, c1, c2, init);
+            d[i] = di;
+            x[i] = xi;
+        }
     }
 }
 
 // Chebyshev step with the Schwarz smoother: z = wgt o acc (acc = QQ^T of the
 // combined local solutions), d = c1 d + c2 z, x += d (x = d when `init`)
+template <bool V4>
 __global__ void cheb_w_kernel(int64_t n, VSet vs, int64_t ld, const float *__restrict__ wgt,
                               const float *__restrict__ acc, float *__restrict__ d,
                               float *__restrict__ x, float c1, float c2, int init)
@@ -439,10 +608,33 @@ __global__ void cheb_w_kernel(int64_t n, VSet vs, int64_t ld, const float *__res
     acc += v * ld;
     d += v * ld;
     x += v * ld;
-    GRID_LOOP(i, n) {
-        const float di = (init ? 0.0f : c1 * d[i]) + c2 * wgt[i] * acc[i];
-        d[i] = di;
-        x[i] = init ? di : x[i] + di;
+    auto pt = [&](float wg, float ac, float &dd, float &xx) {
+        const float di = (init ? 0.0f : c1 * dd) + c2 * wg * ac;
+        dd = di;
+        xx = init ? di : xx + di;
+    };
+    if constexpr (V4) {
+        GRID_LOOP(i, n >> 2) {
+            const float4 wv = FLOAT4_AT(wgt, i), av = FLOAT4_AT(acc, i);
+            float4 dv = make_float4(0.0f, 0.0f, 0.0f, 0.0f), xv = dv;
+            if (!init) {
+                dv = FLOAT4_AT(d, i);
+                xv = FLOAT4_AT(x, i);
+            }
+            pt(wv.x, av.x, dv.x, xv.x);
+            pt(wv.y, av.y, dv.y, xv.y);
+            pt(wv.z, av.z, dv.z, xv.z);
+            pt(wv.w, av.w, dv.w, xv.w);
+            reinterpret_cast<float4 *>(d)[i] = dv;
+            reinterpret_cast<float4 *>(x)[i] = xv;
+        }
+    } else {
+        GRID_LOOP(i, n) {
+            float di = init ? 0.0f : d[i], xi = init ? 0.0f : x[i];
+            pt(wgt[i], acc[i], di, xi);
+            d[i] = di;
+            x[i] = xi;
+        }
     }
 }
 
@@ -613,6 +805,15 @@ __global__ void axpby_kernel(int64_t n, const double *__restrict__ x, double a, 
         hipLaunchKernelGGL(kern, dim3(red_grid(len_), (unsigned)(vs_).n), dim3(kRB), 0, s_, \
                            __VA_ARGS__);                                                    \
         SEM_HIP(hipGetLastError());                                                         \
+    } while (0)
+// the 16-byte form of a vector kernel when ok_, else the one-value form; the
+// grid (and so the number of partial records) is the same for both
+#define LAUNCH_B_V4(ok_, kern, len_, vs_, s_, ...)                                          \
+    do {                                                                                    \
+        if (ok_)                                                                            \
+            LAUNCH_B(kern<true>, len_, vs_, s_, __VA_ARGS__);                               \
+        else                                                                                \
+            LAUNCH_B(kern<false>, len_, vs_, s_, __VA_ARGS__);                              \
     } while (0)
 #define LAUNCH_1B(kern, vs_, s_, ...)                                                       \
     do {                                                                                    \
@@ -863,7 +1064,11 @@ static int smooth_step(const Level &L, int l, sem_handle h, const VSet &vs, int 
 {
     const int64_t n = L.nL;
     if (smoother == SEM_SMOOTH_JACOBI) {
-        LAUNCH_B(cheb_fused_kernel, n, vs, s, n, vs, n, r, t, L.Dinv32, d, x, c1, c2, init);
+        if (vec4_ok(n, n, {r, t, L.Dinv32, d, x}))
+            LAUNCH_B(cheb_fused_kernel<true>, n / 4, vs, s, n, vs, n, r, t, L.Dinv32, d, x, c1, c2,
+                     init);
+        else
+            LAUNCH_B(cheb_fused_kernel<false>, n, vs, s, n, vs, n, r, t, L.Dinv32, d, x, c1, c2, init);
         return SEM_OK;
     }
     Workspace &w = h->ws;
@@ -871,8 +1076,13 @@ static int smooth_step(const Level &L, int l, sem_handle h, const VSet &vs, int 
     float *acc = w.sz_acc[l];
     SEM_TRY(launch_schwarz(L, ras, r, t, w.sz_U, acc, vs, h1, h2, s));
     SEM_TRY(launch_gs_multi<float>(L, acc, n, vs, s, nullptr, 0));
-    LAUNCH_B(cheb_w_kernel, n, vs, s, n, vs, n, (const float *)(ras ? L.W32 : L.sz_w),
-             (const float *)acc, d, x, c1, c2, init);
+    const float *wgt = ras ? L.W32 : L.sz_w;
+    if (vec4_ok(n, n, {wgt, acc, d, x}))
+        LAUNCH_B(cheb_w_kernel<true>, n / 4, vs, s, n, vs, n, wgt, (const float *)acc, d, x, c1, c2,
+                 init);
+    else
+        LAUNCH_B(cheb_w_kernel<false>, n, vs, s, n, vs, n, wgt, (const float *)acc, d, x, c1, c2,
+                 init);
     return SEM_OK;
 }
 
@@ -1014,6 +1224,7 @@ static int pcg_iterations(sem_handle h, const Level &L, const VSet &vs, const do
     const int64_t n = L.nL;
     const int nbv = red_grid(n);
     const int *skip = &kv.sc[0].done;
+    const bool v4 = vec4_ok(n, kv.ldx, {kv.x}) && vec4_ok(n, n, {kv.r, kv.p, kv.w, L.Dinv, L.W});
     for (int c = 0; c < iters; ++c) {
         const int it = first_iter + c;
         const int parity = (it - 1) & 1;
@@ -1021,12 +1232,12 @@ static int pcg_iterations(sem_handle h, const Level &L, const VSet &vs, const do
         SEM_TRY(launch_ax_multi<double>(L, L.G, L.B, L.D, kv.p, n, kv.w, n, vs, h1, h2, k,
                                         ws.partial_ax, ws.pst_ax, &nbax, s, skip, kScStride));
         SEM_TRY(launch_gs_multi<double>(L, kv.w, n, vs, s, skip, kScStride));
-        LAUNCH_B(pcg_update_fused_kernel, n, vs, s, n, vs, n, kv.ldx, kv.sc, parity,
-                 (const double *)ws.partial_ax, ws.pst_ax, nbax, (const double *)kv.p,
-                 (const double *)kv.w, L.Dinv, L.W, kv.x, kv.r, ws.partial, ws.pst);
-        LAUNCH_B(pcg_p_fused_kernel, n, vs, s, n, vs, n, kv.sc, parity, it,
-                 (const double *)ws.partial, ws.pst, (int64_t)nbv, L.Dinv, (const double *)kv.r,
-                 kv.p);
+        LAUNCH_B_V4(v4, pcg_update_fused_kernel, n, vs, s, n, vs, n, kv.ldx, kv.sc, parity,
+                    (const double *)ws.partial_ax, ws.pst_ax, nbax, (const double *)kv.p,
+                    (const double *)kv.w, L.Dinv, L.W, kv.x, kv.r, ws.partial, ws.pst);
+        LAUNCH_B_V4(v4, pcg_p_fused_kernel, n, vs, s, n, vs, n, kv.sc, parity, it,
+                    (const double *)ws.partial, ws.pst, (int64_t)nbv, L.Dinv, (const double *)kv.r,
+                    kv.p);
     }
     return SEM_OK;
 }
@@ -1551,13 +1762,16 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
         VSet act = live_set(w, all);
         const int nbv = red_grid(n);
         const int *skip = &w.sc[0].done;
+        const bool v4 = vec4_ok(n, ld, {x}) && vec4_ok(n, n, {w.r, w.p, w.w, r32, z32, F.W, F.W32});
         VSet cycled{0, 0u};  // vectors whose coarse counts are still to be read
         if (act.n > 0) {
             SEM_TRY(vcycle_run(h, act, cfg, o->use_graphs != 0, s));
-            LAUNCH_B(dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
-                     (const float *)z32, (const double *)w.r, (const double *)w.r, w.partial, w.pst);
-            LAUNCH_B(fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, 1, (const double *)w.partial,
-                     w.pst, (int64_t)nbv, (const float *)z32, F.W32, w.p, 1);
+            LAUNCH_B_V4(v4, dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
+                        (const float *)z32, (const double *)w.r, (const double *)w.r, w.partial,
+                        w.pst);
+            LAUNCH_B_V4(v4, fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, 1,
+                        (const double *)w.partial, w.pst, (int64_t)nbv, (const float *)z32, F.W32,
+                        w.p, 1);
             cycled = act;
         }
         for (int it = 0; act.n > 0; ++it) {
@@ -1567,9 +1781,9 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
                                             nullptr, w.partial_ax, w.pst_ax, &nbax, s, skip,
                                             kScStride));
             SEM_TRY(launch_gs_multi<double>(F, w.w, n, act, s, skip, kScStride));
-            LAUNCH_B(fcg_update_fused_kernel, n, act, s, n, act, n, ld, w.sc, parity,
-                     (const double *)w.partial_ax, w.pst_ax, nbax, (const double *)w.p,
-                     (const double *)w.w, F.W, x, w.r, r32, w.partial, w.pst);
+            LAUNCH_B_V4(v4, fcg_update_fused_kernel, n, act, s, n, act, n, ld, w.sc, parity,
+                        (const double *)w.partial_ax, w.pst_ax, nbax, (const double *)w.p,
+                        (const double *)w.w, F.W, x, w.r, r32, w.partial, w.pst);
             LAUNCH_1B(fin_conv_kernel, act, s, act, (const double *)w.partial, w.pst, (int64_t)nbv,
                       w.sc);
             // one host synchronisation per iteration: outer scalars, and the
@@ -1581,11 +1795,12 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
             act = live_set(w, act);
             if (act.n == 0) break;
             SEM_TRY(vcycle_run(h, act, cfg, o->use_graphs != 0, s));
-            LAUNCH_B(dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
-                     (const float *)z32, (const double *)w.w, (const double *)w.r, w.partial, w.pst);
-            LAUNCH_B(fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, parity,
-                     (const double *)w.partial, w.pst, (int64_t)nbv, (const float *)z32, F.W32, w.p,
-                     0);
+            LAUNCH_B_V4(v4, dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
+                        (const float *)z32, (const double *)w.w, (const double *)w.r, w.partial,
+                        w.pst);
+            LAUNCH_B_V4(v4, fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, parity,
+                        (const double *)w.partial, w.pst, (int64_t)nbv, (const float *)z32, F.W32,
+                        w.p, 0);
             cycled = act;
         }
     }
