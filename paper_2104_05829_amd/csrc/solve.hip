@@ -22,10 +22,14 @@ namespace semx {
 
 constexpr int kRB = 256;          // reduction block size
 constexpr int kMaxRedBlocks = 1024;
+constexpr int kRedMinPerThread = 4;  // entries per thread before a second block is used
 
+// blocks of the vector kernels over n entries: at most kMaxRedBlocks, and at
+// least kRedMinPerThread entries per thread, so a small level's kernels
+// dispatch few blocks and leave few partial records for the next kernel
 static int red_grid(int64_t n)
 {
-    const int64_t nb = (n + kRB - 1) / kRB;
+    const int64_t nb = (n + (int64_t)kRB * kRedMinPerThread - 1) / ((int64_t)kRB * kRedMinPerThread);
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb, kMaxRedBlocks));
 }
 
