@@ -33,9 +33,10 @@ static int red_grid(int64_t n)
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb, kMaxRedBlocks));
 }
 
-// float4 access is possible: n and ld multiples of 4, every array (null
+// the vectorised forms apply (float4 per lane for FP32 streams, a double2
+// pair per lane for FP64 ones): n and ld multiples of 4, every array (null
 // entries ignored) 16-byte aligned
-static bool vec4_ok(int64_t n, int64_t ld, std::initializer_list<const void *> ptrs)
+static bool vec_ok(int64_t n, int64_t ld, std::initializer_list<const void *> ptrs)
 {
     if ((n | ld) & 3) return false;
     for (const void *p : ptrs)
@@ -124,33 +125,29 @@ __device__ inline void sum_partials(const double *partial, int64_t nb, double (&
     for (int q = 0; q < NV; ++q) res[q] = bc[q];
 }
 
-// four consecutive values g*4 .. g*4+3 as 16-byte accesses (arrays 16-byte
-// aligned, checked by the launching code)
-__device__ inline void ld4(const double *p, int64_t g, double (&o)[4])
+// Paired forms of the FP64 vector kernels: lane work on two consecutive
+// points, one double2 (16 bytes) per FP64 array and one float2 per FP32 array
+// (arrays 16-byte aligned, checked by the launching code).
+// two consecutive values g*2, g*2+1 as one access
+__device__ inline void ld2(const double *p, int64_t g, double (&o)[2])
 {
-    const double2 a = reinterpret_cast<const double2 *>(p)[2 * g];
-    const double2 b = reinterpret_cast<const double2 *>(p)[2 * g + 1];
+    const double2 a = reinterpret_cast<const double2 *>(p)[g];
     o[0] = a.x;
     o[1] = a.y;
-    o[2] = b.x;
-    o[3] = b.y;
 }
-__device__ inline void st4(double *p, int64_t g, const double (&o)[4])
+__device__ inline void st2(double *p, int64_t g, const double (&o)[2])
 {
-    reinterpret_cast<double2 *>(p)[2 * g] = make_double2(o[0], o[1]);
-    reinterpret_cast<double2 *>(p)[2 * g + 1] = make_double2(o[2], o[3]);
+    reinterpret_cast<double2 *>(p)[g] = make_double2(o[0], o[1]);
 }
-__device__ inline void ld4(const float *p, int64_t g, float (&o)[4])
+__device__ inline void ld2(const float *p, int64_t g, float (&o)[2])
 {
-    const float4 a = reinterpret_cast<const float4 *>(p)[g];
+    const float2 a = reinterpret_cast<const float2 *>(p)[g];
     o[0] = a.x;
     o[1] = a.y;
-    o[2] = a.z;
-    o[3] = a.w;
 }
-__device__ inline void st4(float *p, int64_t g, const float (&o)[4])
+__device__ inline void st2(float *p, int64_t g, const float (&o)[2])
 {
-    reinterpret_cast<float4 *>(p)[g] = make_float4(o[0], o[1], o[2], o[3]);
+    reinterpret_cast<float2 *>(p)[g] = make_float2(o[0], o[1]);
 }
 
 // ------------------------------------------------------------------ vectors
@@ -278,7 +275,7 @@ __global__ void fin_init_kernel(VSet vs, const double *partial, int64_t pst, int
 // (p, A_L p) in the same fixed order, so all blocks hold the same alpha;
 // x += alpha p; r -= alpha QQ^T(A_L p) (w already assembled); partials
 // (W r Dinv r, W r r).  rz2[parity] is the current (r, z).
-template <bool V4>
+template <bool PAIR>
 __global__ void pcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t ldx,
                                         KrylovScalars *sc, int parity,
                                         const double *__restrict__ pax, int64_t pst_ax, int64_t nbax,
@@ -312,17 +309,17 @@ __global__ void pcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t 
         sc->alpha = a;
     }
     double s[2] = {0.0, 0.0};
-    if constexpr (V4) {
-        GRID_LOOP(g, n >> 2) {
-            double pp[4], ww[4], xx[4], rr[4], wt[4], dd[4];
-            ld4(p, g, pp);
-            ld4(w, g, ww);
-            ld4(x, g, xx);
-            ld4(r, g, rr);
-            ld4(W, g, wt);
-            ld4(Dinv, g, dd);
+    if constexpr (PAIR) {
+        GRID_LOOP(g, n >> 1) {
+            double pp[2], ww[2], xx[2], rr[2], wt[2], dd[2];
+            ld2(p, g, pp);
+            ld2(w, g, ww);
+            ld2(x, g, xx);
+            ld2(r, g, rr);
+            ld2(W, g, wt);
+            ld2(Dinv, g, dd);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < 2; ++k) {
                 xx[k] += a * pp[k];
                 const double ri = rr[k] - a * ww[k];
                 rr[k] = ri;
@@ -330,8 +327,8 @@ __global__ void pcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t 
                 s[0] += wr * dd[k] * ri;
                 s[1] += wr * ri;
             }
-            st4(x, g, xx);
-            st4(r, g, rr);
+            st2(x, g, xx);
+            st2(r, g, rr);
         }
     } else {
         GRID_LOOP(i, n) {
@@ -349,7 +346,7 @@ __global__ void pcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t 
 // Jacobi-PCG direction update with beta and the convergence decision taken
 // by every block from the update's partials (identical in all blocks);
 // block 0 records them.  `iter` is the 1-based number of this iteration.
-template <bool V4>
+template <bool PAIR>
 __global__ void pcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars *sc, int parity,
                                    int iter, const double *__restrict__ pu, int64_t pst, int64_t nbu,
                                    const double *__restrict__ Dinv, const double *__restrict__ r,
@@ -375,15 +372,15 @@ __global__ void pcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars
     }
     if (stop) return;
     const double be = rz / sc->rz2[parity];
-    if constexpr (V4) {
-        GRID_LOOP(g, n >> 2) {
-            double dd[4], rr[4], pp[4];
-            ld4(Dinv, g, dd);
-            ld4(r, g, rr);
-            ld4(p, g, pp);
+    if constexpr (PAIR) {
+        GRID_LOOP(g, n >> 1) {
+            double dd[2], rr[2], pp[2];
+            ld2(Dinv, g, dd);
+            ld2(r, g, rr);
+            ld2(p, g, pp);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) pp[k] = dd[k] * rr[k] + be * pp[k];
-            st4(p, g, pp);
+            for (int k = 0; k < 2; ++k) pp[k] = dd[k] * rr[k] + be * pp[k];
+            st2(p, g, pp);
         }
     } else {
         GRID_LOOP(i, n) p[i] = Dinv[i] * r[i] + be * p[i];
@@ -393,7 +390,7 @@ __global__ void pcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars
 // flexible-CG update: alpha from the operator partials, x += alpha p,
 // r -= alpha QQ^T(A_L p), r32 = FP32 copy of r (the V-cycle input);
 // partial (W r r)
-template <bool V4>
+template <bool PAIR>
 __global__ void fcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t ldx,
                                         KrylovScalars *sc, int parity,
                                         const double *__restrict__ pax, int64_t pst_ax, int64_t nbax,
@@ -427,26 +424,26 @@ __global__ void fcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t 
         sc->alpha = a;
     }
     double s[1] = {0.0};
-    if constexpr (V4) {
-        GRID_LOOP(g, n >> 2) {
-            double pp[4], ww[4], xx[4], rr[4], wt[4];
-            float rf[4];
-            ld4(p, g, pp);
-            ld4(w, g, ww);
-            ld4(x, g, xx);
-            ld4(r, g, rr);
-            ld4(W, g, wt);
+    if constexpr (PAIR) {
+        GRID_LOOP(g, n >> 1) {
+            double pp[2], ww[2], xx[2], rr[2], wt[2];
+            float rf[2];
+            ld2(p, g, pp);
+            ld2(w, g, ww);
+            ld2(x, g, xx);
+            ld2(r, g, rr);
+            ld2(W, g, wt);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < 2; ++k) {
                 xx[k] += a * pp[k];
                 const double ri = rr[k] - a * ww[k];
                 rr[k] = ri;
                 rf[k] = (float)ri;
                 s[0] += wt[k] * ri * ri;
             }
-            st4(x, g, xx);
-            st4(r, g, rr);
-            st4(r32, g, rf);
+            st2(x, g, xx);
+            st2(r, g, rr);
+            st2(r32, g, rf);
         }
     } else {
         GRID_LOOP(i, n) {
@@ -462,7 +459,7 @@ __global__ void fcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t 
 
 // (z, w)_W and (z, r)_W for assembled w, z the FP32 V-cycle output taken to
 // FP64 (W = 0 on Dirichlet copies applies the restriction)
-template <bool V4>
+template <bool PAIR>
 __global__ void dot_zw_kernel(int64_t n, VSet vs, int64_t ld, const KrylovScalars *sc,
                               const double *__restrict__ W, const float *__restrict__ z,
                               const double *__restrict__ wa, const double *__restrict__ r,
@@ -474,16 +471,16 @@ __global__ void dot_zw_kernel(int64_t n, VSet vs, int64_t ld, const KrylovScalar
     wa += v * ld;
     r += v * ld;
     double s[2] = {0.0, 0.0};
-    if constexpr (V4) {
-        GRID_LOOP(g, n >> 2) {
-            double wt[4], ww[4], rr[4];
-            float zz[4];
-            ld4(W, g, wt);
-            ld4(z, g, zz);
-            ld4(wa, g, ww);
-            ld4(r, g, rr);
+    if constexpr (PAIR) {
+        GRID_LOOP(g, n >> 1) {
+            double wt[2], ww[2], rr[2];
+            float zz[2];
+            ld2(W, g, wt);
+            ld2(z, g, zz);
+            ld2(wa, g, ww);
+            ld2(r, g, rr);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < 2; ++k) {
                 const double wz = wt[k] * (double)zz[k];
                 s[0] += wz * ww[k];
                 s[1] += wz * rr[k];
@@ -503,7 +500,7 @@ __global__ void dot_zw_kernel(int64_t n, VSet vs, int64_t ld, const KrylovScalar
 // = -alpha (z_new, A p) / rz_old (r_new - r_old = -alpha A p), taken by every
 // block from the partials of dot_zw_kernel; first = 1 gives p = z.  z is the
 // FP32 V-cycle output, zero on Dirichlet copies (mask W32 > 0).
-template <bool V4>
+template <bool PAIR>
 __global__ void fcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars *sc, int parity,
                                    const double *__restrict__ pz, int64_t pst, int64_t nbz,
                                    const float *__restrict__ z, const float *__restrict__ W32,
@@ -530,16 +527,16 @@ __global__ void fcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars
         }
     }
     if (bad) return;
-    if constexpr (V4) {
-        GRID_LOOP(g, n >> 2) {
-            float zz[4], wt[4];
-            double pp[4];
-            ld4(z, g, zz);
-            ld4(W32, g, wt);
-            ld4(p, g, pp);
+    if constexpr (PAIR) {
+        GRID_LOOP(g, n >> 1) {
+            float zz[2], wt[2];
+            double pp[2];
+            ld2(z, g, zz);
+            ld2(W32, g, wt);
+            ld2(p, g, pp);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) pp[k] = (wt[k] > 0.0f ? (double)zz[k] : 0.0) + be * pp[k];
-            st4(p, g, pp);
+            for (int k = 0; k < 2; ++k) pp[k] = (wt[k] > 0.0f ? (double)zz[k] : 0.0) + be * pp[k];
+            st2(p, g, pp);
         }
     } else {
         GRID_LOOP(i, n) p[i] = (W32[i] > 0.0f ? (double)z[i] : 0.0) + be * p[i];
@@ -810,9 +807,10 @@ __global__ void axpby_kernel(int64_t n, const double *__restrict__ x, double a, 
                            __VA_ARGS__);                                                    \
         SEM_HIP(hipGetLastError());                                                         \
     } while (0)
-// the 16-byte form of a vector kernel when ok_, else the one-value form; the
-// grid (and so the number of partial records) is the same for both
-#define LAUNCH_B_V4(ok_, kern, len_, vs_, s_, ...)                                          \
+// the vectorised form of a vector kernel (kern<true>) when ok_, else the
+// one-value form; the grid (and so the number of partial records) is the same
+// for both
+#define LAUNCH_B_VEC(ok_, kern, len_, vs_, s_, ...)                                          \
     do {                                                                                    \
         if (ok_)                                                                            \
             LAUNCH_B(kern<true>, len_, vs_, s_, __VA_ARGS__);                               \
@@ -1068,7 +1066,7 @@ static int smooth_step(const Level &L, int l, sem_handle h, const VSet &vs, int 
 {
     const int64_t n = L.nL;
     if (smoother == SEM_SMOOTH_JACOBI) {
-        if (vec4_ok(n, n, {r, t, L.Dinv32, d, x}))
+        if (vec_ok(n, n, {r, t, L.Dinv32, d, x}))
             LAUNCH_B(cheb_fused_kernel<true>, n / 4, vs, s, n, vs, n, r, t, L.Dinv32, d, x, c1, c2,
                      init);
         else
@@ -1081,7 +1079,7 @@ static int smooth_step(const Level &L, int l, sem_handle h, const VSet &vs, int 
     SEM_TRY(launch_schwarz(L, ras, r, t, w.sz_U, acc, vs, h1, h2, s));
     SEM_TRY(launch_gs_multi<float>(L, acc, n, vs, s, nullptr, 0));
     const float *wgt = ras ? L.W32 : L.sz_w;
-    if (vec4_ok(n, n, {wgt, acc, d, x}))
+    if (vec_ok(n, n, {wgt, acc, d, x}))
         LAUNCH_B(cheb_w_kernel<true>, n / 4, vs, s, n, vs, n, wgt, (const float *)acc, d, x, c1, c2,
                  init);
     else
@@ -1228,7 +1226,7 @@ static int pcg_iterations(sem_handle h, const Level &L, const VSet &vs, const do
     const int64_t n = L.nL;
     const int nbv = red_grid(n);
     const int *skip = &kv.sc[0].done;
-    const bool v4 = vec4_ok(n, kv.ldx, {kv.x}) && vec4_ok(n, n, {kv.r, kv.p, kv.w, L.Dinv, L.W});
+    const bool vec = vec_ok(n, kv.ldx, {kv.x}) && vec_ok(n, n, {kv.r, kv.p, kv.w, L.Dinv, L.W});
     for (int c = 0; c < iters; ++c) {
         const int it = first_iter + c;
         const int parity = (it - 1) & 1;
@@ -1236,10 +1234,10 @@ static int pcg_iterations(sem_handle h, const Level &L, const VSet &vs, const do
         SEM_TRY(launch_ax_multi<double>(L, L.G, L.B, L.D, kv.p, n, kv.w, n, vs, h1, h2, k,
                                         ws.partial_ax, ws.pst_ax, &nbax, s, skip, kScStride));
         SEM_TRY(launch_gs_multi<double>(L, kv.w, n, vs, s, skip, kScStride));
-        LAUNCH_B_V4(v4, pcg_update_fused_kernel, n, vs, s, n, vs, n, kv.ldx, kv.sc, parity,
+        LAUNCH_B_VEC(vec, pcg_update_fused_kernel, n, vs, s, n, vs, n, kv.ldx, kv.sc, parity,
                     (const double *)ws.partial_ax, ws.pst_ax, nbax, (const double *)kv.p,
                     (const double *)kv.w, L.Dinv, L.W, kv.x, kv.r, ws.partial, ws.pst);
-        LAUNCH_B_V4(v4, pcg_p_fused_kernel, n, vs, s, n, vs, n, kv.sc, parity, it,
+        LAUNCH_B_VEC(vec, pcg_p_fused_kernel, n, vs, s, n, vs, n, kv.sc, parity, it,
                     (const double *)ws.partial, ws.pst, (int64_t)nbv, L.Dinv, (const double *)kv.r,
                     kv.p);
     }
@@ -1766,14 +1764,14 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
         VSet act = live_set(w, all);
         const int nbv = red_grid(n);
         const int *skip = &w.sc[0].done;
-        const bool v4 = vec4_ok(n, ld, {x}) && vec4_ok(n, n, {w.r, w.p, w.w, r32, z32, F.W, F.W32});
+        const bool vec = vec_ok(n, ld, {x}) && vec_ok(n, n, {w.r, w.p, w.w, r32, z32, F.W, F.W32});
         VSet cycled{0, 0u};  // vectors whose coarse counts are still to be read
         if (act.n > 0) {
             SEM_TRY(vcycle_run(h, act, cfg, o->use_graphs != 0, s));
-            LAUNCH_B_V4(v4, dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
+            LAUNCH_B_VEC(vec, dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
                         (const float *)z32, (const double *)w.r, (const double *)w.r, w.partial,
                         w.pst);
-            LAUNCH_B_V4(v4, fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, 1,
+            LAUNCH_B_VEC(vec, fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, 1,
                         (const double *)w.partial, w.pst, (int64_t)nbv, (const float *)z32, F.W32,
                         w.p, 1);
             cycled = act;
@@ -1785,7 +1783,7 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
                                             nullptr, w.partial_ax, w.pst_ax, &nbax, s, skip,
                                             kScStride));
             SEM_TRY(launch_gs_multi<double>(F, w.w, n, act, s, skip, kScStride));
-            LAUNCH_B_V4(v4, fcg_update_fused_kernel, n, act, s, n, act, n, ld, w.sc, parity,
+            LAUNCH_B_VEC(vec, fcg_update_fused_kernel, n, act, s, n, act, n, ld, w.sc, parity,
                         (const double *)w.partial_ax, w.pst_ax, nbax, (const double *)w.p,
                         (const double *)w.w, F.W, x, w.r, r32, w.partial, w.pst);
             LAUNCH_1B(fin_conv_kernel, act, s, act, (const double *)w.partial, w.pst, (int64_t)nbv,
@@ -1799,10 +1797,10 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
             act = live_set(w, act);
             if (act.n == 0) break;
             SEM_TRY(vcycle_run(h, act, cfg, o->use_graphs != 0, s));
-            LAUNCH_B_V4(v4, dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
+            LAUNCH_B_VEC(vec, dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
                         (const float *)z32, (const double *)w.w, (const double *)w.r, w.partial,
                         w.pst);
-            LAUNCH_B_V4(v4, fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, parity,
+            LAUNCH_B_VEC(vec, fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, parity,
                         (const double *)w.partial, w.pst, (int64_t)nbv, (const float *)z32, F.W32,
                         w.p, 0);
             cycled = act;
