@@ -459,7 +459,6 @@ __global__ void fcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t 
 
 // (z, w)_W and (z, r)_W for assembled w, z the FP32 V-cycle output taken to
 // FP64 (W = 0 on Dirichlet copies applies the restriction)
-template <bool PAIR>
 __global__ void dot_zw_kernel(int64_t n, VSet vs, int64_t ld, const KrylovScalars *sc,
                               const double *__restrict__ W, const float *__restrict__ z,
                               const double *__restrict__ wa, const double *__restrict__ r,
@@ -471,27 +470,10 @@ __global__ void dot_zw_kernel(int64_t n, VSet vs, int64_t ld, const KrylovScalar
     wa += v * ld;
     r += v * ld;
     double s[2] = {0.0, 0.0};
-    if constexpr (PAIR) {
-        GRID_LOOP(g, n >> 1) {
-            double wt[2], ww[2], rr[2];
-            float zz[2];
-            ld2(W, g, wt);
-            ld2(z, g, zz);
-            ld2(wa, g, ww);
-            ld2(r, g, rr);
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const double wz = wt[k] * (double)zz[k];
-                s[0] += wz * ww[k];
-                s[1] += wz * rr[k];
-            }
-        }
-    } else {
-        GRID_LOOP(i, n) {
-            const double wz = W[i] * (double)z[i];
-            s[0] += wz * wa[i];
-            s[1] += wz * r[i];
-        }
+    GRID_LOOP(i, n) {
+        const double wz = W[i] * (double)z[i];
+        s[0] += wz * wa[i];
+        s[1] += wz * r[i];
     }
     block_sum_store<2>(s, partial + v * pst);
 }
@@ -1768,9 +1750,9 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
         VSet cycled{0, 0u};  // vectors whose coarse counts are still to be read
         if (act.n > 0) {
             SEM_TRY(vcycle_run(h, act, cfg, o->use_graphs != 0, s));
-            LAUNCH_B_VEC(vec, dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
-                        (const float *)z32, (const double *)w.r, (const double *)w.r, w.partial,
-                        w.pst);
+            LAUNCH_B(dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
+                     (const float *)z32, (const double *)w.r, (const double *)w.r, w.partial,
+                     w.pst);
             LAUNCH_B_VEC(vec, fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, 1,
                         (const double *)w.partial, w.pst, (int64_t)nbv, (const float *)z32, F.W32,
                         w.p, 1);
@@ -1797,9 +1779,9 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
             act = live_set(w, act);
             if (act.n == 0) break;
             SEM_TRY(vcycle_run(h, act, cfg, o->use_graphs != 0, s));
-            LAUNCH_B_VEC(vec, dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
-                        (const float *)z32, (const double *)w.w, (const double *)w.r, w.partial,
-                        w.pst);
+            LAUNCH_B(dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
+                     (const float *)z32, (const double *)w.w, (const double *)w.r, w.partial,
+                     w.pst);
             LAUNCH_B_VEC(vec, fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, parity,
                         (const double *)w.partial, w.pst, (int64_t)nbv, (const float *)z32, F.W32,
                         w.p, 0);
