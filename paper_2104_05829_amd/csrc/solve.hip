@@ -275,7 +275,6 @@ __global__ void fin_init_kernel(VSet vs, const double *partial, int64_t pst, int
 // (p, A_L p) in the same fixed order, so all blocks hold the same alpha;
 // x += alpha p; r -= alpha QQ^T(A_L p) (w already assembled); partials
 // (W r Dinv r, W r r).  rz2[parity] is the current (r, z).
-template <bool PAIR>
 __global__ void pcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t ldx,
                                         KrylovScalars *sc, int parity,
                                         const double *__restrict__ pax, int64_t pst_ax, int64_t nbax,
@@ -309,36 +308,13 @@ __global__ void pcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t 
         sc->alpha = a;
     }
     double s[2] = {0.0, 0.0};
-    if constexpr (PAIR) {
-        GRID_LOOP(g, n >> 1) {
-            double pp[2], ww[2], xx[2], rr[2], wt[2], dd[2];
-            ld2(p, g, pp);
-            ld2(w, g, ww);
-            ld2(x, g, xx);
-            ld2(r, g, rr);
-            ld2(W, g, wt);
-            ld2(Dinv, g, dd);
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                xx[k] += a * pp[k];
-                const double ri = rr[k] - a * ww[k];
-                rr[k] = ri;
-                const double wr = wt[k] * ri;
-                s[0] += wr * dd[k] * ri;
-                s[1] += wr * ri;
-            }
-            st2(x, g, xx);
-            st2(r, g, rr);
-        }
-    } else {
-        GRID_LOOP(i, n) {
-            x[i] += a * p[i];
-            const double ri = r[i] - a * w[i];
-            r[i] = ri;
-            const double wr = W[i] * ri;
-            s[0] += wr * Dinv[i] * ri;
-            s[1] += wr * ri;
-        }
+    GRID_LOOP(i, n) {
+        x[i] += a * p[i];
+        const double ri = r[i] - a * w[i];
+        r[i] = ri;
+        const double wr = W[i] * ri;
+        s[0] += wr * Dinv[i] * ri;
+        s[1] += wr * ri;
     }
     block_sum_store<2>(s, partial + v * pst);
 }
@@ -346,7 +322,6 @@ __global__ void pcg_update_fused_kernel(int64_t n, VSet vs, int64_t ld, int64_t 
 // Jacobi-PCG direction update with beta and the convergence decision taken
 // by every block from the update's partials (identical in all blocks);
 // block 0 records them.  `iter` is the 1-based number of this iteration.
-template <bool PAIR>
 __global__ void pcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars *sc, int parity,
                                    int iter, const double *__restrict__ pu, int64_t pst, int64_t nbu,
                                    const double *__restrict__ Dinv, const double *__restrict__ r,
@@ -372,19 +347,7 @@ __global__ void pcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars
     }
     if (stop) return;
     const double be = rz / sc->rz2[parity];
-    if constexpr (PAIR) {
-        GRID_LOOP(g, n >> 1) {
-            double dd[2], rr[2], pp[2];
-            ld2(Dinv, g, dd);
-            ld2(r, g, rr);
-            ld2(p, g, pp);
-#pragma unroll
-            for (int k = 0; k < 2; ++k) pp[k] = dd[k] * rr[k] + be * pp[k];
-            st2(p, g, pp);
-        }
-    } else {
-        GRID_LOOP(i, n) p[i] = Dinv[i] * r[i] + be * p[i];
-    }
+    GRID_LOOP(i, n) p[i] = Dinv[i] * r[i] + be * p[i];
 }
 
 // flexible-CG update: alpha from the operator partials, x += alpha p,
@@ -1208,7 +1171,6 @@ static int pcg_iterations(sem_handle h, const Level &L, const VSet &vs, const do
     const int64_t n = L.nL;
     const int nbv = red_grid(n);
     const int *skip = &kv.sc[0].done;
-    const bool vec = vec_ok(n, kv.ldx, {kv.x}) && vec_ok(n, n, {kv.r, kv.p, kv.w, L.Dinv, L.W});
     for (int c = 0; c < iters; ++c) {
         const int it = first_iter + c;
         const int parity = (it - 1) & 1;
@@ -1216,12 +1178,12 @@ static int pcg_iterations(sem_handle h, const Level &L, const VSet &vs, const do
         SEM_TRY(launch_ax_multi<double>(L, L.G, L.B, L.D, kv.p, n, kv.w, n, vs, h1, h2, k,
                                         ws.partial_ax, ws.pst_ax, &nbax, s, skip, kScStride));
         SEM_TRY(launch_gs_multi<double>(L, kv.w, n, vs, s, skip, kScStride));
-        LAUNCH_B_VEC(vec, pcg_update_fused_kernel, n, vs, s, n, vs, n, kv.ldx, kv.sc, parity,
-                    (const double *)ws.partial_ax, ws.pst_ax, nbax, (const double *)kv.p,
-                    (const double *)kv.w, L.Dinv, L.W, kv.x, kv.r, ws.partial, ws.pst);
-        LAUNCH_B_VEC(vec, pcg_p_fused_kernel, n, vs, s, n, vs, n, kv.sc, parity, it,
-                    (const double *)ws.partial, ws.pst, (int64_t)nbv, L.Dinv, (const double *)kv.r,
-                    kv.p);
+        LAUNCH_B(pcg_update_fused_kernel, n, vs, s, n, vs, n, kv.ldx, kv.sc, parity,
+                 (const double *)ws.partial_ax, ws.pst_ax, nbax, (const double *)kv.p,
+                 (const double *)kv.w, L.Dinv, L.W, kv.x, kv.r, ws.partial, ws.pst);
+        LAUNCH_B(pcg_p_fused_kernel, n, vs, s, n, vs, n, kv.sc, parity, it,
+                 (const double *)ws.partial, ws.pst, (int64_t)nbv, L.Dinv, (const double *)kv.r,
+                 kv.p);
     }
     return SEM_OK;
 }
