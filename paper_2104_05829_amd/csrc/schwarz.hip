@@ -19,8 +19,9 @@
 // with N >= 2), the 1D operators and their eigen-decompositions (cyclic
 // Jacobi on M^{-1/2} K M^{-1/2}), and the accumulation lists.
 #include <algorithm>
-#include <thread>
 #include <cmath>
+#include <cstdlib>
+#include <thread>
 #include <numeric>
 #include <vector>
 
@@ -147,9 +148,16 @@ struct SchwarzHost {
     std::vector<float> S, lam, w;
 };
 
-// host threads for the per-element setup work (at most 16)
+// host threads for the per-element setup work: SEM_HOST_THREADS when set to
+// 1..64 (read at every setup), else the hardware concurrency, at most 16.
+// The result does not depend on the count (disjoint per-element ranges, a
+// deterministic merge of sorted runs).
 static int host_threads()
 {
+    if (const char *env = std::getenv("SEM_HOST_THREADS")) {
+        const long v = std::strtol(env, nullptr, 10);
+        if (v >= 1 && v <= 64) return (int)v;
+    }
     const unsigned hc = std::thread::hardware_concurrency();
     return (int)std::max(1u, std::min(16u, hc));
 }
