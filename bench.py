@@ -74,6 +74,48 @@ def measured_traffic():
         return None
 
 
+_ORACLE_TIMING_DIR = None
+
+
+def oracle_timing_lib():
+    """The oracle's all-core timing build (OpenMP over elements, -O3
+    -march=native), compiled on this host into a temporary directory."""
+    global _ORACLE_TIMING_DIR
+    import tempfile
+    import oracle
+    if _ORACLE_TIMING_DIR is None:
+        _ORACLE_TIMING_DIR = tempfile.mkdtemp(prefix="oracle_omp_")
+    return oracle.timing_lib(_ORACLE_TIMING_DIR)
+
+
+class OracleResidual:
+    """True relative residuals ||R (b - QQ^T A_L x)||_W / ||R b||_W of GPU
+    solutions, recomputed by the CPU oracle in FP64 from the mesh alone
+    (its own GLL nodes, geometric factors, element operator and QQ^T; the
+    element loops of the geometry and the operator on all cores through the
+    timing build, which computes bit-identical elements)."""
+
+    def __init__(self, mesh, N=7):
+        import oracle
+        self.oracle = oracle
+        self.N = N
+        xi, rho = oracle.gll(N)
+        self.D = oracle.dhat(N, xi)
+        self.lib = oracle_timing_lib()
+        self.G, self.B, _ = oracle.geometry(N, mesh.x, mesh.y, mesh.z, self.D, rho, _lib=self.lib)
+        self.gid = mesh.gid.reshape(-1)
+        mask = 1.0 - mesh.dirichlet.reshape(-1).astype(np.float64)
+        self.W = mask / oracle.multiplicity(self.gid)
+        self.mask = mask
+
+    def rel(self, x, b, h1, h2):
+        o = self.oracle
+        Ax = o.qqt(self.gid, o.ax(self.N, self.D, self.G, x, h1=h1, h2=h2, B=self.B, _lib=self.lib))
+        r = self.mask * (b - Ax)
+        bm = self.mask * b
+        return float(np.sqrt(np.sum(self.W * r * r) / np.sum(self.W * bm * bm)))
+
+
 def bench_operator(args, torch, sem_mod, inputs):
     N = 7
     mesh = sem_mod.box_mesh(16, 16, 16, N, deform="cyclic", amp=0.05, bc="neumann")
@@ -162,6 +204,9 @@ def bench_pcg(args, torch, sem_mod, inputs):
         Bt = torch.stack([s.gs(B * torch.tensor(inputs.gaussian_per_node(mesh.gid, seed), device="cuda"))
                           * (W > 0) for seed in (30, 31, 32)[: args.pcg_rhs]])
         for pre in pres:
+            # untimed first lockstep call: grows the solver workspace to the batch
+            s.solve_multi(Bt, tol=1e-8, h1=1.0, h2=10.0, precond=pre, maxit=20000,
+                          coarse_tol=args.coarse_tol, coarse_maxit=args.coarse_maxit)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             X, sts, rc = s.solve_multi(Bt, tol=1e-8, h1=1.0, h2=10.0, precond=pre, maxit=20000,
@@ -229,6 +274,46 @@ def bench_pcg(args, torch, sem_mod, inputs):
                                            "sample": "the 5x5x5 corner block (125 elements), numpy one thread, "
                                                      "scaled per element",
                                            "ms_scaled": round(dt * 1e3 * mesh.E / 125, 1)}
+    # phase breakdown of one more solve of the first right-hand side with the
+    # library's event timers (not part of the timed solves above)
+    phases = {}
+    b0 = s.gs(B * torch.tensor(inputs.gaussian_per_node(mesh.gid, 30), device="cuda")) * (W > 0)
+    for pre in pres:
+        _, st, _ = s.solve(b0, tol=1e-8, h1=1.0, h2=10.0, precond=pre, maxit=20000, timers=1,
+                           coarse_tol=args.coarse_tol, coarse_maxit=args.coarse_maxit)
+        phases[pre] = {k: round(st[k], 3) for k in ("ms_ax", "ms_gs", "ms_vec", "ms_prec", "ms_coarse")}
+        phases[pre]["ms_solve"] = round(st["ms_solve"], 3)
+    # the element operator alone on this mesh (out of the 256 MB last-level
+    # cache: 1.07 GB per Poisson apply), HIP events on the stream it runs on
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wv = torch.empty_like(b0)
+    ooc = {}
+    for label, h2v, bpp in (("poisson", 0.0, 64), ("helmholtz", 10.0, 72)):
+        for _ in range(3):
+            s.ax(b0, wv, h1=1.0, h2=h2v)
+        ev0.record(stream)
+        for _ in range(10):
+            s.ax(b0, wv, h1=1.0, h2=h2v)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_a = ev0.elapsed_time(ev1) / 10
+        gbs = bpp * s.n_local / (ms_a * 1e-3) / 1e9
+        ooc[label] = {"ms": round(ms_a, 4), "algorithmic_bytes": bpp * s.n_local,
+                      "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del wv
+    # every solution's true residual recomputed by the CPU oracle
+    oracle_res = {}
+    if not args.no_cpu:
+        log("[bench] pcg: oracle residuals of the 32^3 solutions")
+        orc = OracleResidual(mesh)
+        for pre in pres:
+            oracle_res[pre] = []
+            for r in res[pre]:
+                f = inputs.gaussian_per_node(mesh.gid, r["seed"])
+                bh = s.gs(B * torch.tensor(f, device="cuda")) * (W > 0)
+                oracle_res[pre].append(float(f"{orc.rel(r['x'].cpu().numpy(), bh.cpu().numpy(), 1.0, 10.0):.3e}"))
+        del orc
     # difference between the two solutions (W-weighted, relative)
     diffs = []
     for a, bb in zip(res.get("pmg", []), res.get("jacobi", [])):
@@ -251,6 +336,10 @@ def bench_pcg(args, torch, sem_mod, inputs):
                     "status": [r["rc"] for r in runs]}
         if pre == "pmg":
             out[pre]["coarse_iters"] = [r["coarse_iters"] for r in runs]
+        if pre in oracle_res:
+            out[pre]["oracle_true_rel_res"] = oracle_res[pre]
+        out[pre]["phases_ms_rhs0"] = phases[pre]
+    out["ax_out_of_cache"] = ooc
     for pre, v in lock.items():
         out[pre + "_lockstep"] = v
         v["speedup_vs_independent"] = round(out[pre]["ms_total"] / v["ms_total"], 3)
@@ -393,7 +482,6 @@ def bench_large(args, torch, sem_mod, inputs):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     f = torch.tensor(inputs.gaussian_per_node(mesh.gid, 50), device="cuda")
-    del mesh
     b = s.rhs(f)
     del f
     inf = s.info()
@@ -416,6 +504,7 @@ def bench_large(args, torch, sem_mod, inputs):
            "n_unique": inf["n_unique"], "n_local": nL, "mesh_s": round(t_mesh, 2),
            "setup_s": round(t_setup, 3), "ms_ax_fp64": round(ms_ax, 4),
            "ax_fp64_GBps": round(AX_BYTES_PER_POINT * nL / (ms_ax * 1e-3) / 1e9, 1)}
+    xs = {}
     for pre in ("pmg", "jacobi"):
         s.solve(b, tol=1e-8, precond=pre, maxit=1)  # builds and caches the preconditioner
         torch.cuda.synchronize()
@@ -425,12 +514,30 @@ def bench_large(args, torch, sem_mod, inputs):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[pre] = {"ms": round(dt * 1e3, 2), "iters": st["iters"],
-                    "true_rel_res": float(f"{st['true_rel_res']:.3e}"), "status": rc}
+                    "true_rel_res": float(f"{st['true_rel_res']:.3e}"), "status": rc,
+                    "gdof_per_s_per_iter": round(inf["n_unique"] * st["iters"] / dt / 1e9, 3)}
         if pre == "pmg":
             out[pre]["coarse_iters"] = st["coarse_iters"]
+            _, stt, _ = s.solve(b, tol=1e-8, precond=pre, maxit=50000, timers=1,
+                                coarse_tol=args.coarse_tol, coarse_maxit=args.coarse_maxit)
+            out[pre]["phases_ms"] = {k: round(stt[k], 3) for k in
+                                     ("ms_solve", "ms_ax", "ms_gs", "ms_vec", "ms_prec", "ms_coarse")}
+        xs[pre] = x.cpu().numpy()
         del x
+    W, _ = s.weights()
+    Wh = W.cpu().numpy()
+    dx = xs["pmg"] - xs["jacobi"]
+    out["rel_diff_pmg_vs_jacobi"] = float(f"{np.sqrt(np.sum(Wh * dx * dx) / np.sum(Wh * xs['jacobi'] ** 2)):.3e}")
     out["speedup_pmg_vs_jacobi"] = round(out["jacobi"]["ms"] / out["pmg"]["ms"], 3)
+    bh = b.cpu().numpy()
     s.free()
+    del b, W
+    if not args.no_cpu:
+        log("[bench] large: oracle residuals of the 64x64x32 solutions")
+        orc = OracleResidual(mesh)
+        for pre in ("pmg", "jacobi"):
+            out[pre]["oracle_true_rel_res"] = float(f"{orc.rel(xs[pre], bh, 1.0, 0.0):.3e}")
+        del orc
     return out
 
 
@@ -464,9 +571,12 @@ def bench_c1(args, torch, sem_mod, inputs, with_cpu):
         lv = solvers.Level(7, m.x, m.y, m.z, m.gid, m.dirichlet)
         bo = lv.rhs(3 * math.pi ** 2 * ue)
         t0 = time.perf_counter()
-        _, ito, _ = solvers.pcg_jacobi(lv, bo, tol=1e-10)
+        xo, ito, _ = solvers.pcg_jacobi(lv, bo, tol=1e-10)
         out["cpu_oracle"] = {"ms": round((time.perf_counter() - t0) * 1e3, 1), "iters": ito,
                              "cores": 1, "kind": "oracle"}
+        xg = x.cpu().numpy()
+        out["rel_err_vs_oracle_solution"] = float(
+            f"{np.sqrt(np.sum(lv.W * (xg - xo) ** 2) / np.sum(lv.W * xo ** 2)):.3e}")
     s.free()
     return out
 
@@ -527,23 +637,35 @@ def bench_adjoint(args, torch, sem_mod, inputs):
 
 def cpu_baseline(mesh, seconds):
     """The oracle's Ax + QQ^T on the full 16^3 N=7 mesh, repeated until
-    about `seconds` of CPU time; single-threaded C (no OpenMP)."""
+    about `seconds` of CPU time: the checked build (single-threaded C, -O2),
+    then the all-core timing build (OpenMP over elements, -O3 -march=native;
+    its QQ^T, a sort by global pointer and a sequential accumulation, stays on
+    one thread).  Returns both per-apply times with their split."""
     import oracle
     xi, _ = oracle.gll(7)
     D = oracle.dhat(7, xi)
     G, B, _ = oracle.geometry(7, mesh.x, mesh.y, mesh.z)
     from paper_2104_05829_amd import inputs
     u = inputs.uniform_lvector(mesh.n_local, 2)
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        w = oracle.ax(7, D, G, u)
-        oracle.qqt(mesh.gid, w)
-        reps += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = (time.perf_counter() - t0) / reps
-    return dt, reps
+    out = {}
+    for label, lib_, budget in (("one_thread", None, seconds), ("all_cores", oracle_timing_lib(), seconds / 2)):
+        reps, t_ax, t_gs = 0, 0.0, 0.0
+        t0 = time.perf_counter()
+        while True:
+            ta = time.perf_counter()
+            w = oracle.ax(7, D, G, u, _lib=lib_)
+            tb = time.perf_counter()
+            oracle.qqt(mesh.gid, w)
+            tc = time.perf_counter()
+            t_ax += tb - ta
+            t_gs += tc - tb
+            reps += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        out[label] = {"ms_apply": (time.perf_counter() - t0) * 1e3 / reps, "ms_ax": t_ax * 1e3 / reps,
+                      "ms_qqt": t_gs * 1e3 / reps, "reps": reps,
+                      "threads": 1 if lib_ is None else lib_.oracle_threads()}
+    return out
 
 
 def main():
@@ -562,8 +684,8 @@ def main():
     ap.add_argument("--pcg-precond", choices=("both", "pmg", "jacobi"), default="both")
     ap.add_argument("--coarse-tol", type=float, default=1e-2)
     ap.add_argument("--coarse-maxit", type=int, default=20)
-    ap.add_argument("--large", action="store_true",
-                    help="also time the 64x64x32 Poisson case (PMG-FCG vs Jacobi-PCG to 1e-8)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 64x64x32 Poisson case (PMG-FCG vs Jacobi-PCG to 1e-8)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (counter scaling)")
     args = ap.parse_args()
@@ -640,12 +762,23 @@ def main():
         line["copy_probe"] = {"bytes_read": n * 8, "bytes_written": n * 8, "launches": 3}
     if not args.no_cpu:
         log(f"[bench] cpu baseline: oracle Ax + QQ^T, about {args.cpu_seconds} s")
-        dt, reps = cpu_baseline(op["mesh"], args.cpu_seconds)
+        cb = cpu_baseline(op["mesh"], args.cpu_seconds)
+        one, allc = cb["one_thread"], cb["all_cores"]
         line["cpu_baseline"] = {
-            "value": round(op["nU"] / dt / 1e9, 6), "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} applies of the oracle's element operator + QQ^T on the full 16^3 N=7 "
-                      f"mesh, single-threaded C, {dt * 1e3:.1f} ms per apply, host "
-                      f"{os.cpu_count()} logical CPUs",
+            "value": round(op["nU"] / (one["ms_apply"] * 1e-3) / 1e9, 6), "unit": "GDOF/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{one['reps']} applies of the oracle's element operator + QQ^T on the full 16^3 N=7 "
+                      f"mesh, single-threaded C (-O2), {one['ms_apply']:.1f} ms per apply "
+                      f"(Ax {one['ms_ax']:.1f} + QQ^T {one['ms_qqt']:.1f}), host {os.cpu_count()} logical "
+                      f"CPUs, {len(os.sched_getaffinity(0))} available",
+            "all_cores": {
+                "value": round(op["nU"] / (allc["ms_apply"] * 1e-3) / 1e9, 6), "unit": "GDOF/s",
+                "cores": allc["threads"], "kind": "oracle",
+                "build": "same C source, -O3 -march=native -fopenmp, OpenMP over elements in Ax; "
+                         "QQ^T (sort by pointer + accumulation) on one thread",
+                "ms_apply": round(allc["ms_apply"], 2), "ms_ax": round(allc["ms_ax"], 2),
+                "ms_qqt": round(allc["ms_qqt"], 2), "reps": allc["reps"],
+                "ax_speedup_vs_one_thread": round(one["ms_ax"] / allc["ms_ax"], 2)},
         }
     if not args.no_pcg:
         log("[bench] pcg: 32^3 Helmholtz, FCG+FP32 p-MG vs FP64 Jacobi-PCG to 1e-8")
@@ -660,7 +793,7 @@ def main():
         log("[bench] 4^3 Poisson Jacobi-PCG and 8^3 adjoint")
         line["c1"] = bench_c1(args, torch, sem_mod, inputs, not args.no_cpu)
         line["adjoint"] = bench_adjoint(args, torch, sem_mod, inputs)
-    if args.large:
+    if not args.no_large:
         log("[bench] large: 64x64x32 Poisson, FCG+FP32 p-MG vs FP64 Jacobi-PCG to 1e-8")
         line["pcg_large"] = bench_large(args, torch, sem_mod, inputs)
     print(json.dumps(line), flush=True)

@@ -197,6 +197,9 @@ typedef struct {
                             path is switched off (SEM_EINVAL) because one replay was
                             seen to differ from the kernel-by-kernel solve with no
                             cause found. */
+    int timers;          /* 1: time the solver's phases with HIP events on `stream` (fills
+                            the ms_ax .. ms_coarse fields of the stats); adds event records
+                            between kernels and no host synchronisation.  0: off (fields 0) */
 } sem_solve_opts;
 
 typedef struct {
@@ -209,12 +212,24 @@ typedef struct {
     int coarse_iters;      /* total coarsest-level iterations (PMG) */
     int proj_vectors;      /* earlier solutions the initial guess was projected onto */
     double proj_rel_res;   /* ||b - A xbar||_W / ||b||_W of the projected guess xbar */
+    /* Phase times with opts->timers = 1 (else 0): device time between
+     * consecutive phase boundaries on the stream, launch gaps included, summed
+     * over the iteration (for sem_pcg_solve_multi the phases serve every
+     * system at once and each record holds the same totals):
+     *   ms_ax     element operator applications of the outer iteration
+     *   ms_gs     their gather-scatter QQ^T
+     *   ms_vec    vector updates, inner products and convergence decisions
+     *             of the outer iteration (with Jacobi, the preconditioner too)
+     *   ms_prec   p-multigrid V-cycle without its coarsest-level solve
+     *             (smoothing, transfers, level operators)
+     *   ms_coarse coarsest-level Jacobi-PCG inside the V-cycles */
+    double ms_ax, ms_gs, ms_vec, ms_prec, ms_coarse;
 } sem_solve_stats;
 
 /* Fill opts with defaults: h1 = 1, h2 = 0, k = NULL, tol = 1e-8, maxit = 1000,
  * Jacobi, check_every = 8, cheb_degree = 2, lanczos_steps = 20,
  * interval [0.1, 1.1] lambda_max, coarse_tol = 1e-2, coarse_maxit = 20,
- * zero_guess = 1, proj_dim = 0, smoother = SEM_SMOOTH_JACOBI, use_graphs = 0. */
+ * zero_guess = 1, proj_dim = 0, smoother = SEM_SMOOTH_JACOBI, use_graphs = 0, timers = 0. */
 SEM_API void sem_solve_opts_default(sem_solve_opts *opts);
 
 /*

@@ -36,29 +36,55 @@ def build(force: bool = True) -> str:
     return _SO
 
 
+_timing = {}
+
+
+def build_timing(dest_dir: str) -> str:
+    """The same C file built for the all-core CPU timing, not for checking:
+    -O3 -march=native (the host it runs on) and OpenMP over the elements of
+    oracle_ax; -ffp-contract=off keeps every element's arithmetic that of the
+    checked build.  Built into dest_dir on the host that times it."""
+    so = os.path.join(dest_dir, "liboracle_omp.so")
+    cmd = ["gcc", "-std=gnu11", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared",
+           "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", so, "-lm"]
+    subprocess.check_call(cmd)
+    return so
+
+
+def timing_lib(dest_dir: str):
+    """ctypes handle of the all-core timing build (see build_timing)."""
+    if dest_dir not in _timing:
+        _timing[dest_dir] = _bind(ctypes.CDLL(build_timing(dest_dir)))
+    return _timing[dest_dir]
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
             build()
-        L = ctypes.CDLL(_SO)
-        d = ctypes.POINTER(ctypes.c_double)
-        i64 = ctypes.c_int64
-        p64 = ctypes.POINTER(ctypes.c_int64)
-        p32 = ctypes.POINTER(ctypes.c_int32)
-        L.oracle_gll.argtypes = [ctypes.c_int, d, d]
-        L.oracle_dhat.argtypes = [ctypes.c_int, d, d]
-        L.oracle_interp.argtypes = [ctypes.c_int, d, ctypes.c_int, d, d]
-        L.oracle_geometry.argtypes = [ctypes.c_int, i64, d, d, d, d, d, d, d, d]
-        L.oracle_ax.argtypes = [ctypes.c_int, i64, d, d, d, d, ctypes.c_double, ctypes.c_double, d, d]
-        L.oracle_diag.argtypes = [ctypes.c_int, i64, d, d, d, d, ctypes.c_double, ctypes.c_double, d]
-        L.oracle_qqt.argtypes = [i64, p64, d]
-        L.oracle_multiplicity.argtypes = [i64, p64, p32]
-        L.oracle_gs_maps.argtypes = [i64, p64, p64, p64, p32, p32]
-        L.oracle_grad_k.argtypes = [ctypes.c_int, i64, d, d, ctypes.c_double, d, d, d]
-        L.oracle_interp_lvec.argtypes = [ctypes.c_int, ctypes.c_int, i64, d, d, d]
-        _lib = L
+        _lib = _bind(ctypes.CDLL(_SO))
     return _lib
+
+
+def _bind(L):
+    d = ctypes.POINTER(ctypes.c_double)
+    i64 = ctypes.c_int64
+    p64 = ctypes.POINTER(ctypes.c_int64)
+    p32 = ctypes.POINTER(ctypes.c_int32)
+    L.oracle_gll.argtypes = [ctypes.c_int, d, d]
+    L.oracle_dhat.argtypes = [ctypes.c_int, d, d]
+    L.oracle_interp.argtypes = [ctypes.c_int, d, ctypes.c_int, d, d]
+    L.oracle_geometry.argtypes = [ctypes.c_int, i64, d, d, d, d, d, d, d, d]
+    L.oracle_ax.argtypes = [ctypes.c_int, i64, d, d, d, d, ctypes.c_double, ctypes.c_double, d, d]
+    L.oracle_diag.argtypes = [ctypes.c_int, i64, d, d, d, d, ctypes.c_double, ctypes.c_double, d]
+    L.oracle_qqt.argtypes = [i64, p64, d]
+    L.oracle_multiplicity.argtypes = [i64, p64, p32]
+    L.oracle_gs_maps.argtypes = [i64, p64, p64, p64, p32, p32]
+    L.oracle_grad_k.argtypes = [ctypes.c_int, i64, d, d, ctypes.c_double, d, d, d]
+    L.oracle_interp_lvec.argtypes = [ctypes.c_int, ctypes.c_int, i64, d, d, d]
+    L.oracle_threads.restype = ctypes.c_int
+    return L
 
 
 def _d(a):
@@ -111,9 +137,9 @@ def interp_matrix(xs, xt):
     return J
 
 
-def geometry(N: int, x, y, z, D=None, rho=None, allow_bad: bool = False):
+def geometry(N: int, x, y, z, D=None, rho=None, allow_bad: bool = False, _lib=None):
     """Geometric factors G [6, nL] (G11,G12,G13,G22,G23,G33), mass B [nL],
-    Jacobian J [nL]; eqs. (grad), (vBu), (gij)."""
+    Jacobian J [nL]; eqs. (grad), (vBu), (gij).  _lib: a timing build."""
     if D is None:
         xi, rho = gll(N)
         D = dhat(N, xi)
@@ -125,7 +151,7 @@ def geometry(N: int, x, y, z, D=None, rho=None, allow_bad: bool = False):
     G = np.zeros((6, nL))
     B = np.zeros(nL)
     J = np.zeros(nL)
-    rc = lib().oracle_geometry(N, E, _d(np.ascontiguousarray(D)), _d(np.ascontiguousarray(rho)),
+    rc = (_lib or lib()).oracle_geometry(N, E, _d(np.ascontiguousarray(D)), _d(np.ascontiguousarray(rho)),
                                _d(x), _d(y), _d(z), _d(G), _d(B), _d(J))
     if rc == -6 and not allow_bad:
         raise ValueError("mesh has a nonpositive Jacobian")
@@ -134,14 +160,15 @@ def geometry(N: int, x, y, z, D=None, rho=None, allow_bad: bool = False):
     return G, B, J
 
 
-def ax(N: int, D, G, u, h1: float = 1.0, h2: float = 0.0, B=None, k=None):
-    """Unassembled w_L = h1 A_L(k) u_L + h2 B_L u_L, eq. (Ae)."""
+def ax(N: int, D, G, u, h1: float = 1.0, h2: float = 0.0, B=None, k=None, _lib=None):
+    """Unassembled w_L = h1 A_L(k) u_L + h2 B_L u_L, eq. (Ae).  _lib: a
+    timing build (timing_lib) instead of the checked one."""
     u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
     E = u.size // (N + 1) ** 3
     w = np.zeros_like(u)
     kk = None if k is None else np.ascontiguousarray(k, dtype=np.float64).reshape(-1)
     BB = None if B is None else np.ascontiguousarray(B, dtype=np.float64).reshape(-1)
-    _check(lib().oracle_ax(N, E, _d(np.ascontiguousarray(D)), _d(np.ascontiguousarray(G)), _d(BB),
+    _check((_lib or lib()).oracle_ax(N, E, _d(np.ascontiguousarray(D)), _d(np.ascontiguousarray(G)), _d(BB),
                            _d(kk), h1, h2, _d(u), _d(w)), "ax")
     return w
 

@@ -19,6 +19,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_EINVAL -1
@@ -155,6 +158,10 @@ int oracle_geometry(int N, int64_t E, const double *D, const double *rho,
     int64_t nL = E * nq * nq * nq;
     const double *X[3] = {x, y, z};
     int bad = 0;
+    /* elements independent: split over threads in the timing build only */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(| : bad)
+#endif
     for (int64_t e = 0; e < E; ++e)
         for (int k = 0; k < nq; ++k)
             for (int j = 0; j < nq; ++j)
@@ -218,11 +225,24 @@ int oracle_ax(int N, int64_t E, const double *D, const double *G, const double *
     int nq = N + 1;
     int np = nq * nq * nq;
     int64_t nL = E * np;
+    int failed = 0;
+    /* Elements are independent.  The separate timing build (-fopenmp) splits
+     * the element loop over threads, each with its own scratch; the checked
+     * build compiles without OpenMP and runs it as one plain loop.  The
+     * arithmetic of an element is the same either way. */
+#ifdef _OPENMP
+#pragma omp parallel reduction(| : failed)
+#endif
+    {
     double *wr = malloc(sizeof(double) * np);
     double *ws = malloc(sizeof(double) * np);
     double *wt = malloc(sizeof(double) * np);
-    if (!wr || !ws || !wt) { free(wr); free(ws); free(wt); return ORC_EINVAL; }
+    if (!wr || !ws || !wt) failed = 1;
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
     for (int64_t e = 0; e < E; ++e) {
+        if (failed) continue;
         for (int k = 0; k < nq; ++k)
             for (int j = 0; j < nq; ++j)
                 for (int i = 0; i < nq; ++i) {
@@ -257,7 +277,18 @@ int oracle_ax(int N, int64_t E, const double *D, const double *G, const double *
                 }
     }
     free(wr); free(ws); free(wt);
-    return ORC_OK;
+    }
+    return failed ? ORC_EINVAL : ORC_OK;
+}
+
+/* Threads the element loop of oracle_ax uses (1 in the checked build). */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /*

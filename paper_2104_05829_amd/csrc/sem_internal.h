@@ -150,6 +150,18 @@ struct Level {
     double sz_lmax = 0.0;  // lambda_max(M^{-1} A) estimate for the current key
 };
 
+// Phase timers of a solve (sem_solve_opts.timers): a chain of events on the
+// solver's stream, restarted after every host synchronisation; the interval
+// that ends at event i is charged to phase ph[i] (-1: the chain's start).
+enum SolvePhase { kPhaseAx = 0, kPhaseGs, kPhaseVec, kPhasePrec, kPhaseCoarse, kPhases };
+struct PhaseClock {
+    bool on = false;
+    std::vector<hipEvent_t> ev;  // pool, created on first use
+    std::vector<int> ph;
+    int n = 0;                   // events recorded in the current chain
+    double ms[kPhases] = {};
+};
+
 struct Workspace {
     int64_t nL = 0;
     int nv = 0;        // vectors per array (batched solves), grown on demand
@@ -197,6 +209,7 @@ struct Workspace {
     int vg_next = 0;
     bool vg_broken = false;  // capture failed once: launch kernel by kernel
     hipStream_t cap = nullptr;
+    PhaseClock clk;
 };
 
 struct PrecondKey {

@@ -802,9 +802,62 @@ static void free_projection(Workspace &w)
     w.proj_L = w.proj_nv = 0;
 }
 
+// ------------------------------------------------------------ phase clock
+constexpr int kClockEvents = 512;
+
+static int clock_begin(Workspace &w, bool on)
+{
+    PhaseClock &c = w.clk;
+    c.on = on;
+    c.n = 0;
+    for (double &m : c.ms) m = 0.0;
+    if (on && c.ev.empty()) {
+        c.ev.assign(kClockEvents, nullptr);
+        c.ph.assign(kClockEvents, -1);
+        for (auto &e : c.ev) SEM_HIP(hipEventCreate(&e));
+    }
+    return SEM_OK;
+}
+
+// Charge the intervals of the current chain; the stream has reached its last
+// event (after a host synchronisation), or `wait` waits for it.  The chain
+// restarts empty: the idle time of the host round trip is charged to nothing.
+static int clock_flush(Workspace &w, bool wait)
+{
+    PhaseClock &c = w.clk;
+    if (!c.on || c.n == 0) return SEM_OK;
+    if (wait) SEM_HIP(hipEventSynchronize(c.ev[c.n - 1]));
+    for (int i = 1; i < c.n; ++i) {
+        float ms = 0.0f;
+        SEM_HIP(hipEventElapsedTime(&ms, c.ev[i - 1], c.ev[i]));
+        if (c.ph[i] >= 0) c.ms[c.ph[i]] += ms;
+    }
+    c.n = 0;
+    return SEM_OK;
+}
+
+// A phase boundary on `s`: the device time since the previous boundary is
+// phase p's (p = -1, or an empty chain: only the chain's start is set).
+static int clock_mark(Workspace &w, int p, hipStream_t s)
+{
+    PhaseClock &c = w.clk;
+    if (!c.on) return SEM_OK;
+    if (c.n == (int)c.ev.size()) {  // pool used up: charge it, continue the chain from here
+        SEM_TRY(clock_flush(w, true));
+        p = -1;
+    }
+    SEM_HIP(hipEventRecord(c.ev[c.n], s));
+    c.ph[c.n] = c.n == 0 ? -1 : p;
+    ++c.n;
+    return SEM_OK;
+}
+
 void free_workspace(sem_handle h)
 {
     Workspace &w = h->ws;
+    for (auto &e : w.clk.ev)
+        if (e) (void)hipEventDestroy(e);
+    w.clk.ev.clear();
     for (auto &g : w.vg)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (w.cap) (void)hipStreamDestroy(w.cap);
@@ -1160,12 +1213,28 @@ struct KrylovVecs {
     KrylovScalars *sc;
 };
 
+// Reduction buffers and inverse diagonal of a Jacobi-PCG: the handle's
+// workspace and level data, or the allocation-free solve's static scratch.
+struct PcgBufs {
+    double *partial;
+    int64_t pst;
+    double *partial_ax;
+    int64_t pst_ax;
+    const double *Dinv;
+};
+
+static PcgBufs ws_bufs(sem_handle h, const Level &L)
+{
+    return PcgBufs{h->ws.partial, h->ws.pst, h->ws.partial_ax, h->ws.pst_ax, L.Dinv};
+}
+
 // enqueue Jacobi-PCG iterations first_iter .. first_iter+iters-1 (1-based)
 // on level L for the batch vs: operator with fused (p, A_L p), QQ^T, update
 // with alpha, and direction update with beta and the convergence decision --
 // four kernels per iteration, no single-block reduction kernels
 static int pcg_iterations(sem_handle h, const Level &L, const VSet &vs, const double *k, double h1,
-                          double h2, const KrylovVecs &kv, int first_iter, int iters, hipStream_t s)
+                          double h2, const KrylovVecs &kv, const PcgBufs &pb, int first_iter,
+                          int iters, hipStream_t s, bool timed = false)
 {
     Workspace &ws = h->ws;
     const int64_t n = L.nL;
@@ -1176,24 +1245,26 @@ static int pcg_iterations(sem_handle h, const Level &L, const VSet &vs, const do
         const int parity = (it - 1) & 1;
         int64_t nbax = 0;
         SEM_TRY(launch_ax_multi<double>(L, L.G, L.B, L.D, kv.p, n, kv.w, n, vs, h1, h2, k,
-                                        ws.partial_ax, ws.pst_ax, &nbax, s, skip, kScStride));
+                                        pb.partial_ax, pb.pst_ax, &nbax, s, skip, kScStride));
+        if (timed) SEM_TRY(clock_mark(ws, kPhaseAx, s));
         SEM_TRY(launch_gs_multi<double>(L, kv.w, n, vs, s, skip, kScStride));
+        if (timed) SEM_TRY(clock_mark(ws, kPhaseGs, s));
         LAUNCH_B(pcg_update_fused_kernel, n, vs, s, n, vs, n, kv.ldx, kv.sc, parity,
-                 (const double *)ws.partial_ax, ws.pst_ax, nbax, (const double *)kv.p,
-                 (const double *)kv.w, L.Dinv, L.W, kv.x, kv.r, ws.partial, ws.pst);
+                 (const double *)pb.partial_ax, pb.pst_ax, nbax, (const double *)kv.p,
+                 (const double *)kv.w, pb.Dinv, L.W, kv.x, kv.r, pb.partial, pb.pst);
         LAUNCH_B(pcg_p_fused_kernel, n, vs, s, n, vs, n, kv.sc, parity, it,
-                 (const double *)ws.partial, ws.pst, (int64_t)nbv, L.Dinv, (const double *)kv.r,
+                 (const double *)pb.partial, pb.pst, (int64_t)nbv, pb.Dinv, (const double *)kv.r,
                  kv.p);
+        if (timed) SEM_TRY(clock_mark(ws, kPhaseVec, s));
     }
     return SEM_OK;
 }
 
 // start a Jacobi-PCG on level L for the batch vs: x given (Ax computed) or zero
-static int pcg_start(sem_handle h, const Level &L, const VSet &vs, const double *k, double h1,
-                     double h2, const double *b, int64_t ldb, const KrylovVecs &kv, bool zero,
-                     double tol, int maxit, const BbRef &ref, hipStream_t s)
+static int pcg_start(const Level &L, const VSet &vs, const double *k, double h1, double h2,
+                     const double *b, int64_t ldb, const KrylovVecs &kv, const PcgBufs &pb,
+                     bool zero, double tol, int maxit, const BbRef &ref, hipStream_t s)
 {
-    Workspace &ws = h->ws;
     const int64_t n = L.nL;
     const double *Ax = nullptr;
     if (zero) {
@@ -1205,9 +1276,9 @@ static int pcg_start(sem_handle h, const Level &L, const VSet &vs, const double 
         SEM_TRY(launch_gs_multi<double>(L, kv.w, n, vs, s, nullptr, 0));
         Ax = kv.w;
     }
-    LAUNCH_B(pcg_init_kernel, n, vs, s, n, vs, ldb, b, n, Ax, L.Dinv, L.W, kv.r, kv.p,
-             (float *)nullptr, ws.partial, ws.pst, 1);
-    LAUNCH_1B(fin_init_kernel, vs, s, vs, (const double *)ws.partial, ws.pst, (int64_t)red_grid(n),
+    LAUNCH_B(pcg_init_kernel, n, vs, s, n, vs, ldb, b, n, Ax, pb.Dinv, L.W, kv.r, kv.p,
+             (float *)nullptr, pb.partial, pb.pst, 1);
+    LAUNCH_1B(fin_init_kernel, vs, s, vs, (const double *)pb.partial, pb.pst, (int64_t)red_grid(n),
               kv.sc, tol, maxit, ref);
     return SEM_OK;
 }
@@ -1223,9 +1294,12 @@ static int vcycle(sem_handle h, int l, const VSet &vs, const SolveCfg &cfg, hipS
     if (l == lc) {
         double *b = (double *)w.mg_r[l];
         const KrylovVecs kv{(double *)w.mg_x[l], n, w.c_r, w.c_p, w.c_w, w.sc_c};
-        SEM_TRY(pcg_start(h, L, vs, nullptr, cfg.h1, cfg.h2, b, n, kv, true, cfg.coarse_tol,
+        SEM_TRY(clock_mark(w, kPhasePrec, s));
+        const PcgBufs pb = ws_bufs(h, L);
+        SEM_TRY(pcg_start(L, vs, nullptr, cfg.h1, cfg.h2, b, n, kv, pb, true, cfg.coarse_tol,
                           cfg.coarse_maxit, BbRef{}, s));
-        SEM_TRY(pcg_iterations(h, L, vs, nullptr, cfg.h1, cfg.h2, kv, 1, cfg.coarse_maxit, s));
+        SEM_TRY(pcg_iterations(h, L, vs, nullptr, cfg.h1, cfg.h2, kv, pb, 1, cfg.coarse_maxit, s));
+        SEM_TRY(clock_mark(w, kPhaseCoarse, s));
         return SEM_OK;
     }
     float *r = (float *)w.mg_r[l], *x = (float *)w.mg_x[l], *t = (float *)w.mg_t[l],
@@ -1675,16 +1749,26 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
         ldbs = n;
     }
     const bool zero = proj || o->zero_guess != 0;
+    // phase timers: a new event chain after every host synchronisation
+    SEM_TRY(clock_begin(w, o->timers != 0));
+    auto sync_point = [&](bool coarse) -> int {
+        SEM_TRY(read_scalars(h, coarse, s));
+        SEM_TRY(clock_flush(w, false));
+        return clock_mark(w, -1, s);
+    };
+    SEM_TRY(clock_mark(w, -1, s));
     if (!pmg) {
-        SEM_TRY(pcg_start(h, F, all, o->k, o->h1, o->h2, bs, ldbs, kv, zero, o->tol, o->maxit, ref,
-                          s));
-        SEM_TRY(read_scalars(h, false, s));
+        SEM_TRY(pcg_start(F, all, o->k, o->h1, o->h2, bs, ldbs, kv, ws_bufs(h, F), zero, o->tol,
+                          o->maxit, ref, s));
+        SEM_TRY(clock_mark(w, kPhaseVec, s));
+        SEM_TRY(sync_point(false));
         VSet act = live_set(w, all);
         int it = 0;
         while (act.n > 0) {
-            SEM_TRY(pcg_iterations(h, F, act, o->k, o->h1, o->h2, kv, it + 1, cfg.check_every, s));
+            SEM_TRY(pcg_iterations(h, F, act, o->k, o->h1, o->h2, kv, ws_bufs(h, F), it + 1,
+                                   cfg.check_every, s, true));
             it += cfg.check_every;
-            SEM_TRY(read_scalars(h, false, s));
+            SEM_TRY(sync_point(false));
             act = live_set(w, act);
         }
     } else {
@@ -1704,7 +1788,8 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
                  (double *)nullptr, r32, w.partial, w.pst, 0);
         LAUNCH_1B(fin_init_kernel, all, s, all, (const double *)w.partial, w.pst,
                   (int64_t)red_grid(n), w.sc, o->tol, o->maxit, ref);
-        SEM_TRY(read_scalars(h, false, s));
+        SEM_TRY(clock_mark(w, kPhaseVec, s));
+        SEM_TRY(sync_point(false));
         VSet act = live_set(w, all);
         const int nbv = red_grid(n);
         const int *skip = &w.sc[0].done;
@@ -1712,12 +1797,14 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
         VSet cycled{0, 0u};  // vectors whose coarse counts are still to be read
         if (act.n > 0) {
             SEM_TRY(vcycle_run(h, act, cfg, o->use_graphs != 0, s));
+            SEM_TRY(clock_mark(w, kPhasePrec, s));
             LAUNCH_B(dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
                      (const float *)z32, (const double *)w.r, (const double *)w.r, w.partial,
                      w.pst);
             LAUNCH_B_VEC(vec, fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, 1,
                         (const double *)w.partial, w.pst, (int64_t)nbv, (const float *)z32, F.W32,
                         w.p, 1);
+            SEM_TRY(clock_mark(w, kPhaseVec, s));
             cycled = act;
         }
         for (int it = 0; act.n > 0; ++it) {
@@ -1726,30 +1813,40 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
             SEM_TRY(launch_ax_multi<double>(F, F.G, F.B, F.D, w.p, n, w.w, n, act, o->h1, o->h2,
                                             nullptr, w.partial_ax, w.pst_ax, &nbax, s, skip,
                                             kScStride));
+            SEM_TRY(clock_mark(w, kPhaseAx, s));
             SEM_TRY(launch_gs_multi<double>(F, w.w, n, act, s, skip, kScStride));
+            SEM_TRY(clock_mark(w, kPhaseGs, s));
             LAUNCH_B_VEC(vec, fcg_update_fused_kernel, n, act, s, n, act, n, ld, w.sc, parity,
                         (const double *)w.partial_ax, w.pst_ax, nbax, (const double *)w.p,
                         (const double *)w.w, F.W, x, w.r, r32, w.partial, w.pst);
             LAUNCH_1B(fin_conv_kernel, act, s, act, (const double *)w.partial, w.pst, (int64_t)nbv,
                       w.sc);
+            SEM_TRY(clock_mark(w, kPhaseVec, s));
             // one host synchronisation per iteration: outer scalars, and the
             // coarse-solve counts of the V-cycle that preceded this update
-            SEM_TRY(read_scalars(h, cycled.n > 0, s));
+            SEM_TRY(sync_point(cycled.n > 0));
             for (int q = 0; q < cycled.n; ++q)
                 coarse_total[cycled.at(q)] += w.host_sc[kMaxRhs + cycled.at(q)].iters;
             cycled = VSet{0, 0u};
             act = live_set(w, act);
             if (act.n == 0) break;
             SEM_TRY(vcycle_run(h, act, cfg, o->use_graphs != 0, s));
+            SEM_TRY(clock_mark(w, kPhasePrec, s));
             LAUNCH_B(dot_zw_kernel, n, act, s, n, act, n, (const KrylovScalars *)w.sc, F.W,
                      (const float *)z32, (const double *)w.w, (const double *)w.r, w.partial,
                      w.pst);
             LAUNCH_B_VEC(vec, fcg_p_fused_kernel, n, act, s, n, act, n, w.sc, parity,
                         (const double *)w.partial, w.pst, (int64_t)nbv, (const float *)z32, F.W32,
                         w.p, 0);
+            SEM_TRY(clock_mark(w, kPhaseVec, s));
             cycled = act;
         }
     }
+    SEM_TRY(clock_flush(w, true));
+    const bool timed = w.clk.on;
+    double phase_ms[kPhases];
+    std::copy(w.clk.ms, w.clk.ms + kPhases, phase_ms);
+    w.clk.on = false;
     std::vector<KrylovScalars> hs(w.host_sc, w.host_sc + nv);
     if (proj)
         for (int v = 0; v < nv; ++v) SEM_TRY(proj_update(h, v, b + v * ld, x + v * ld, o->h1, o->h2, s));
@@ -1771,6 +1868,11 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
             st[v].coarse_iters = coarse_total[v];
             st[v].proj_vectors = proj_used[v];
             st[v].proj_rel_res = proj_rel[v];
+            st[v].ms_ax = timed ? phase_ms[kPhaseAx] : 0.0;
+            st[v].ms_gs = timed ? phase_ms[kPhaseGs] : 0.0;
+            st[v].ms_vec = timed ? phase_ms[kPhaseVec] : 0.0;
+            st[v].ms_prec = timed ? phase_ms[kPhasePrec] : 0.0;
+            st[v].ms_coarse = timed ? phase_ms[kPhaseCoarse] : 0.0;
         }
         if (q.status == SEM_EBREAKDOWN) {
             if (rc != SEM_EBREAKDOWN)
@@ -1867,6 +1969,7 @@ void sem_solve_opts_default(sem_solve_opts *o)
     o->proj_dim = 0;
     o->smoother = SEM_SMOOTH_JACOBI;
     o->use_graphs = 0;
+    o->timers = 0;
 }
 
 int sem_smoother_apply(sem_handle h, int level, int smoother, double h1, double h2, const float *r,

@@ -52,14 +52,17 @@ class SemSolveOpts(ctypes.Structure):
                 ("lanczos_steps", ctypes.c_int), ("cheb_lo", ctypes.c_double),
                 ("cheb_hi", ctypes.c_double), ("coarse_tol", ctypes.c_double),
                 ("coarse_maxit", ctypes.c_int), ("zero_guess", ctypes.c_int),
-                ("proj_dim", ctypes.c_int), ("smoother", ctypes.c_int), ("use_graphs", ctypes.c_int)]
+                ("proj_dim", ctypes.c_int), ("smoother", ctypes.c_int), ("use_graphs", ctypes.c_int),
+                ("timers", ctypes.c_int)]
 
 
 class SemSolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("rel_res", ctypes.c_double),
                 ("true_rel_res", ctypes.c_double), ("ms_solve", ctypes.c_double),
                 ("ms_setup", ctypes.c_double), ("coarse_iters", ctypes.c_int),
-                ("proj_vectors", ctypes.c_int), ("proj_rel_res", ctypes.c_double)]
+                ("proj_vectors", ctypes.c_int), ("proj_rel_res", ctypes.c_double),
+                ("ms_ax", ctypes.c_double), ("ms_gs", ctypes.c_double), ("ms_vec", ctypes.c_double),
+                ("ms_prec", ctypes.c_double), ("ms_coarse", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -2,7 +2,8 @@
 
 Bars: gather-scatter maps and QQ^T values bit-exact; FP64 operator applies
 within 1e-12 relative (2-norm and max-norm, normalised by the reference);
-FP32 level operators within 1e-5 relative of the FP64 oracle; solvers on
+FP32 level operators within 1e-5 relative of the FP64 oracle (every
+p-multigrid level, on coordinates the oracle interpolates itself); solvers on
 outcomes (iterations, true residual, error against the oracle solution)."""
 import math
 
@@ -225,27 +226,56 @@ def test_coarse_levels_match_structured_numbering():
     s.free()
 
 
-@pytest.mark.parametrize("level,N", [(0, 7), (1, 3)])
-def test_fp32_level_operators(level, N):
-    print(f"[gpu] fp32 level {level}", flush=True)
+def _oracle_level_coords(m, levels):
+    """Coordinates of every p-multigrid level by the oracle: each level's nodes
+    interpolated elementwise from the next finer level's (Sec. 3.4, coarse
+    spaces on the same elements; coarse operators by rediscretisation)."""
+    xs = [(m.x.reshape(-1), m.y.reshape(-1), m.z.reshape(-1))]
+    for Nf, Nc in zip(levels[:-1], levels[1:]):
+        xf, _ = oracle.gll(Nf)
+        xc, _ = oracle.gll(Nc)
+        J = oracle.interp_matrix(xf, xc)
+        xs.append(tuple(oracle.interp_lvec(J, a, Nf + 1, Nc + 1) for a in xs[-1]))
+    return xs
+
+
+@pytest.mark.parametrize("levels", [(7, 3, 1), (5, 3, 2, 1)])
+def test_level_operators_match_oracle(levels):
+    """Every p-multigrid level's operator against the oracle's operator on
+    that level's interpolated coordinates: FP64 (h1 A + h2 B, Poisson and
+    Helmholtz) within 1e-12 relative, FP32 within 1e-5 relative, and FP32
+    QQ^T against the oracle's QQ^T of the same FP32 input."""
+    print(f"[gpu] level operators {levels}", flush=True)
     shape = (3, 3, 2)
-    m = _mesh(shape, 7, deform="cyclic")
-    s = Sem(m, levels=(7, 3, 1))
-    inf = s.info(level)
-    u = inputs.uniform_lvector(inf["n_local"], 3)
-    w32 = _host(s.ax_level(level, _dev(u.astype(np.float32)), h1=1.0, h2=10.0))
-    w64 = _host(s.ax_level(level, _dev(u), h1=1.0, h2=10.0))
-    r2, _ = _rel(w32.astype(np.float64), w64)
-    assert r2 < 1e-5
-    v = inputs.uniform_lvector(inf["n_local"], 4)
-    g32 = _host(s.gs_level(level, _dev(v.astype(np.float32))))
-    _, gref = s.weights(level)
-    ref = oracle.qqt(_host(gref), v.astype(np.float32).astype(np.float64))
-    assert np.max(np.abs(g32 - ref)) <= 1e-6 * np.max(np.abs(ref))
-    if level == 0:
-        lv = solvers.Level(N, m.x, m.y, m.z, m.gid, m.dirichlet, 1.0, 10.0)
-        r2, rmax = _rel(w64, lv.ax_local(u))
-        assert r2 <= 1e-12 and rmax <= 1e-12
+    m = _mesh(shape, levels[0], deform="cyclic")
+    s = Sem(m, levels=levels)
+    coords = _oracle_level_coords(m, levels)
+    for lvl, N in enumerate(levels):
+        x, y, z = coords[lvl]
+        xi, rho = oracle.gll(N)
+        D = oracle.dhat(N, xi)
+        G, B, _ = oracle.geometry(N, x, y, z, D, rho)
+        Gl, Bl = s.geometry(lvl)
+        _, gl = s.weights(lvl)
+        gid = _host(gl)
+        u = inputs.uniform_lvector(x.size, 3 + lvl)
+        for h2 in (0.0, 10.0):
+            ref = oracle.ax(N, D, G, u, h1=1.0, h2=h2, B=B)
+            w64 = _host(s.ax_level(lvl, _dev(u), h1=1.0, h2=h2))
+            r2, rmax = _rel(w64, ref)
+            assert r2 <= 1e-12 and rmax <= 1e-12, (lvl, h2, r2, rmax)
+            if lvl < len(levels) - 1:  # smoothed levels carry FP32 data
+                w32 = _host(s.ax_level(lvl, _dev(u.astype(np.float32)), h1=1.0, h2=h2))
+                r2, _ = _rel(w32.astype(np.float64), ref)
+                assert r2 <= 1e-5, (lvl, h2, r2)
+        # the library's B of the level is the oracle's (quadrature on the
+        # interpolated geometry)
+        assert np.max(np.abs(_host(Bl) - B)) <= 1e-13 * np.max(np.abs(B))
+        if lvl < len(levels) - 1:
+            v = inputs.uniform_lvector(x.size, 20 + lvl).astype(np.float32)
+            g32 = _host(s.gs_level(lvl, _dev(v)))
+            ref = oracle.qqt(gid, v.astype(np.float64))
+            assert np.max(np.abs(g32 - ref)) <= 1e-6 * np.max(np.abs(ref)), lvl
     s.free()
 
 

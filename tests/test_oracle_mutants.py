@@ -54,6 +54,12 @@ MUTANTS = [
      "c[1] += D[j * nq + l] * u[IDX(l, i, k, e)];"),
     ("interp_wrong_node", "if (m != j) h *= (xt[i] - xs[m]) / (xs[j] - xs[m]);",
      "if (m != j) h *= (xt[i] - xs[m]) / (xs[i % ns] - xs[m] + (i % ns == m));"),
+    ("interp_lvec_axes_swapped", "s += J[k * ns + c] * J[j * ns + b] * J[i * ns + a]",
+     "s += J[j * ns + c] * J[k * ns + b] * J[i * ns + a]"),
+    ("interp_lvec_transposed_J", "s += J[k * ns + c] * J[j * ns + b] * J[i * ns + a]",
+     "s += J[k * ns + c] * J[j * ns + b] * J[a * nt + i]"),
+    ("interp_lvec_element_stride", "* in[e * pin + a + ns * (b + ns * c)];",
+     "* in[e * pout % (pin * E) + a + ns * (b + ns * c)];"),
 ]
 
 PINS = [
@@ -62,6 +68,8 @@ PINS = [
     lambda gd: t_ref.test_dhat_differentiates_polynomials_exactly(5),
     lambda gd: t_ref.test_dhat_known_entries(3),
     lambda gd: t_ref.test_interp_matrix(),
+    lambda gd: t_ref.test_interp_lvec_reproduces_polynomials(7, 3),
+    lambda gd: t_ref.test_interp_lvec_reproduces_polynomials(2, 5),
     lambda gd: t_geo.test_undeformed_cube_closed_form(3),
     lambda gd: t_geo.test_affine_nonsymmetric_map(),
     lambda gd: t_geo.test_deformed_volume_converges_spectrally(),

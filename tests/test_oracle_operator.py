@@ -101,3 +101,23 @@ def test_operator_symmetry_matrix_free():
     Av = oracle.qqt(m.gid, oracle.ax(N, D, G, v, 1.0, 5.0, B))
     a, b = np.sum(W * v * Au), np.sum(W * u * Av)
     assert abs(a - b) < 1e-12 * max(abs(a), 1.0)
+
+
+def test_timing_build_is_bit_identical(tmp_path):
+    """The all-core timing build of the oracle (OpenMP over elements, -O3
+    -march=native) computes the same geometric factors and element operator,
+    bit for bit, as the checked build."""
+    from paper_2104_05829_amd import inputs
+    N = 5
+    xi, rho = oracle.gll(N)
+    D = oracle.dhat(N, xi)
+    m = inputs.box_mesh(5, 4, 3, xi, deform="cyclic")
+    T = oracle.timing_lib(str(tmp_path))
+    G, B, J = oracle.geometry(N, m.x, m.y, m.z, D, rho)
+    Gt, Bt, Jt = oracle.geometry(N, m.x, m.y, m.z, D, rho, _lib=T)
+    assert np.array_equal(G, Gt) and np.array_equal(B, Bt) and np.array_equal(J, Jt)
+    u = np.random.default_rng(3).uniform(-1, 1, m.n_local)
+    k = np.random.default_rng(4).uniform(0.5, 2, m.n_local)
+    for kw in (dict(), dict(h2=3.0, B=B), dict(h2=3.0, B=B, k=k)):
+        assert np.array_equal(oracle.ax(N, D, G, u, **kw), oracle.ax(N, D, G, u, _lib=T, **kw))
+    assert oracle.lib().oracle_threads() == 1
