@@ -251,6 +251,30 @@ SEM_API int sem_pcg_solve(sem_handle h, const double *b, double *x, const sem_so
                   sem_solve_stats *stats, void *stream);
 
 /*
+ * Allocation-free form of sem_pcg_solve, for callers that cannot allocate
+ * device memory (code under HIP stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same FP64 Jacobi-PCG, one right-hand
+ * side, with every buffer beyond b and x (Krylov scalars, reduction partials,
+ * the inverse diagonal, the vectors r, p, w) in a static device array of
+ * SEM_NOALLOC_SCRATCH_MIB MiB per GPU that the library holds from its first
+ * use on that GPU until the process ends.  b, x, opts, stats and the stream as
+ * for sem_pcg_solve; the iterates, solution and stats equal sem_pcg_solve's
+ * with the Jacobi preconditioner.
+ *   Limits: opts->precond = SEM_PRECOND_JACOBI, proj_dim = 0, timers = 0, and
+ *   n_local <= SEM_NOALLOC_MAX_LOCAL, else SEM_EINVAL with nothing enqueued;
+ *   the current device must be the handle's.
+ *   Calls no hipMalloc/hipFree (nor any allocating library routine); the
+ *   inverse diagonal is recomputed each call (its cost is one operator-sized
+ *   pass).  Every call on a GPU shares that GPU's scratch, so calls that
+ *   overlap on one GPU (several host threads, or streams that run concurrently)
+ *   race and give undefined results; serialise them.  Synchronises `stream`.
+ */
+#define SEM_NOALLOC_SCRATCH_MIB 96
+#define SEM_NOALLOC_MAX_LOCAL 3142880
+SEM_API int sem_pcg_solve_noalloc(sem_handle h, const double *b, double *x, const sem_solve_opts *opts,
+                                  sem_solve_stats *stats, void *stream);
+
+/*
  * Projection of initial guesses for successive right-hand sides (the pressure
  * initial guesses of Sec. 3.4 / Sec. 4, after Fischer, CMAME 163, 1998).  With
  * opts->proj_dim = L > 0 every solve keeps, per right-hand-side slot (slot 0

@@ -179,6 +179,7 @@ static int setup_impl(const sem_mesh *m, const sem_setup_opts *o, hipStream_t s,
     const int nq = N + 1;
     const int64_t nL = E * nq * nq * nq;
     SEM_HIP(hipGetDevice(&h->device));
+    SEM_TRY(noalloc_attach(h->device));
     int levels[kMaxLevels] = {N, 0, 0, 0};
     int nlev = 1;
     if (o && o->pmg) {

@@ -278,6 +278,10 @@ int launch_geometry(const Level &L, const double *x, const double *y, const doub
 template <typename T>
 int launch_diag(const Level &L, const double *k, double h1, double h2, double *d, hipStream_t s);
 
+// look up the allocation-free solve's scratch address on device dev (current);
+// once per device, from sem_setup
+int noalloc_attach(int dev);
+
 int launch_grad_k(const Level &L, const double *u, const double *lam, double h1, double *gk,
                   hipStream_t s);
 

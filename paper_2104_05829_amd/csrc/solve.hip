@@ -14,6 +14,7 @@
 #include <chrono>
 #include <initializer_list>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "sem_internal.h"
@@ -1924,6 +1925,154 @@ int adjoint(sem_handle h, const double *u, const double *g, const sem_solve_opts
     return rc;
 }
 
+
+// ------------------------------------------------ allocation-free Jacobi-PCG
+// Device scratch of sem_pcg_solve_noalloc: the Krylov scalars, the reduction
+// partials, the inverse diagonal Dinv and the vectors r, p, w of one FP64
+// Jacobi-PCG.  One copy per GPU, held from the library's first use on that
+// GPU until the process ends; every call on a GPU shares it (and finds the
+// last call's contents), so calls that overlap on one GPU race.
+constexpr size_t kNoAllocBytes = (size_t)SEM_NOALLOC_SCRATCH_MIB << 20;
+constexpr size_t kNoAllocHead = 256;                             // KrylovScalars
+constexpr int64_t kNoAllocPst = 3 * kMaxRedBlocks;               // vector-kernel partials
+constexpr int64_t kNoAllocPstAx = 8192;                          // operator partials
+constexpr size_t kNoAllocVecOff =
+    kNoAllocHead + sizeof(double) * (size_t)(kNoAllocPst + kNoAllocPstAx);
+static_assert(sizeof(KrylovScalars) <= kNoAllocHead, "scalar record");
+static_assert(kNoAllocVecOff % 256 == 0, "vector alignment");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// the device address of `scratch` on each GPU (the array's name in host code
+// is a host-side stand-in, not a device address)
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch[kNoAllocMaxDevices] = {};
+
+// largest level-0 L-vector the scratch holds: four vectors (Dinv, r, p, w) of
+// a multiple of 32 doubles, so each starts 256-byte aligned
+constexpr int64_t kNoAllocMaxLocal =
+    (int64_t)((kNoAllocBytes - kNoAllocVecOff) / (4 * sizeof(double))) & ~(int64_t)31;
+static_assert(kNoAllocMaxLocal == SEM_NOALLOC_MAX_LOCAL, "limit stated in sem.h");
+
+// Look up the scratch address on device `dev` (current) once; called by
+// sem_setup for the handle's device.
+int noalloc_attach(int dev)
+{
+    if (dev < 0 || dev >= kNoAllocMaxDevices) {
+        set_error("setup: device %d beyond the %d devices the allocation-free solve supports", dev,
+                  kNoAllocMaxDevices);
+        return SEM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev]) return SEM_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        set_error("setup: address of the allocation-free solve's scratch: %s", hipGetErrorString(e));
+        return SEM_EHIP;
+    }
+    g_scratch[dev] = (unsigned char *)p;
+    return SEM_OK;
+}
+
+// host copy of the scalar record, the stream synchronised
+static int read_one_scalar(const KrylovScalars *sc, KrylovScalars *out, hipStream_t s)
+{
+    SEM_HIP(hipMemcpyAsync(out, sc, sizeof(KrylovScalars), hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    return SEM_OK;
+}
+
+// The Jacobi-PCG of pcg_solve for one right-hand side, every buffer beyond
+// b and x in the device scratch: the same kernels in the same order, so the
+// iterates equal those of sem_pcg_solve with the Jacobi preconditioner.
+static int pcg_solve_noalloc(sem_handle h, const double *b, double *x, const sem_solve_opts *o,
+                             sem_solve_stats *st, hipStream_t s)
+{
+    using clk = std::chrono::steady_clock;
+    const Level &F = h->lv[0];
+    const int64_t n = F.nL;
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (h->device >= 0 && h->device < kNoAllocMaxDevices) base = g_scratch[h->device];
+    }
+    if (!base) {
+        set_error("sem_pcg_solve_noalloc: no scratch address for device %d", h->device);
+        return SEM_EHIP;
+    }
+    const int64_t pst_ax = (int64_t)(F.n_cu > 0 ? F.n_cu : 256) * kAxMaxBlocksPerCU + 64;
+    if (pst_ax > kNoAllocPstAx) {
+        set_error("sem_pcg_solve_noalloc: %d compute units exceed the scratch's operator partials",
+                  F.n_cu);
+        return SEM_EINVAL;
+    }
+    const size_t vb = ((size_t)n * sizeof(double) + 255) & ~(size_t)255;
+    KrylovScalars *sc = (KrylovScalars *)base;
+    double *partial = (double *)(base + kNoAllocHead);
+    double *partial_ax = partial + kNoAllocPst;
+    double *Dinv = (double *)(base + kNoAllocVecOff);
+    double *r = (double *)(base + kNoAllocVecOff + vb);
+    double *p = (double *)(base + kNoAllocVecOff + 2 * vb);
+    double *w = (double *)(base + kNoAllocVecOff + 3 * vb);
+    const VSet one = VSet::one();
+    const auto t0 = clk::now();
+    // Dinv of h1 A(k) + h2 B: assembled diagonal (in r), inverted on free copies
+    SEM_TRY(launch_diag<double>(F, o->k, o->h1, o->h2, r, s));
+    SEM_TRY(launch_gs<double>(F, r, s));
+    LAUNCH_V(invert_diag_kernel, n, s, n, F.W, (const double *)r, Dinv, (float *)nullptr);
+    SEM_HIP(hipStreamSynchronize(s));
+    const auto t1 = clk::now();
+    const KrylovVecs kv{x, n, r, p, w, sc};
+    const PcgBufs pb{partial, kNoAllocPst, partial_ax, pst_ax, Dinv};
+    const int check = std::max(1, o->check_every);
+    SEM_TRY(pcg_start(F, one, o->k, o->h1, o->h2, b, n, kv, pb, o->zero_guess != 0, o->tol, o->maxit,
+                      BbRef{}, s));
+    KrylovScalars hs{};
+    SEM_TRY(read_one_scalar(sc, &hs, s));
+    for (int it = 0; !hs.done; it += check) {
+        SEM_TRY(pcg_iterations(h, F, one, o->k, o->h1, o->h2, kv, pb, it + 1, check, s));
+        SEM_TRY(read_one_scalar(sc, &hs, s));
+    }
+    const auto t2 = clk::now();
+    // true residual b - QQ^T A_L x (into w, then r), (W r r, W b b) summed on
+    // the host in block order
+    SEM_TRY(launch_ax_multi<double>(F, F.G, F.B, F.D, x, n, w, n, one, o->h1, o->h2, o->k, nullptr, 0,
+                                    nullptr, s, nullptr, 0));
+    SEM_TRY(launch_gs_multi<double>(F, w, n, one, s, nullptr, 0));
+    LAUNCH_B(pcg_init_kernel, n, one, s, n, one, n, b, n, (const double *)w, (const double *)Dinv,
+             F.W, r, (double *)nullptr, (float *)nullptr, partial, kNoAllocPst, 0);
+    const int nb = red_grid(n);
+    double hp[3 * kMaxRedBlocks];
+    SEM_HIP(hipMemcpyAsync(hp, partial, sizeof(double) * 3 * nb, hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    double rr = 0.0, bb = 0.0;
+    for (int i = 0; i < nb; ++i) {
+        rr += hp[3 * i + 1];
+        bb += hp[3 * i + 2];
+    }
+    const bool conv = hs.status == SEM_OK && (hs.bb == 0.0 || hs.rr <= hs.tol2);
+    if (st) {
+        *st = sem_solve_stats{};
+        st->iters = hs.iters;
+        st->rel_res = hs.bb > 0 ? std::sqrt(std::max(hs.rr, 0.0) / hs.bb) : 0.0;
+        st->converged = conv ? 1 : 0;
+        st->true_rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+        st->ms_setup = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        st->ms_solve = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    }
+    if (hs.status == SEM_EBREAKDOWN) {
+        set_error("sem_pcg_solve_noalloc: breakdown after %d iterations", hs.iters);
+        return SEM_EBREAKDOWN;
+    }
+    if (!conv) {
+        set_error("sem_pcg_solve_noalloc: not converged after %d iterations (rel res %.3e)", hs.iters,
+                  hs.bb > 0 ? std::sqrt(hs.rr / hs.bb) : 0.0);
+        return SEM_ENOCONV;
+    }
+    return SEM_OK;
+}
+
 }  // namespace semx
 
 using namespace semx;
@@ -2086,6 +2235,32 @@ int sem_pcg_solve_multi(sem_handle h, int nrhs, const double *b, double *x, int6
     }
     SEM_TRY(check_solve_opts("sem_pcg_solve_multi", o));
     return pcg_solve(h, nrhs, b, x, ld, o, st, (hipStream_t)stream);
+}
+
+int sem_pcg_solve_noalloc(sem_handle h, const double *b, double *x, const sem_solve_opts *o,
+                          sem_solve_stats *st, void *stream)
+{
+    if (!h || !b || !x || !o) {
+        set_error("sem_pcg_solve_noalloc: null argument");
+        return SEM_EINVAL;
+    }
+    SEM_TRY(check_solve_opts("sem_pcg_solve_noalloc", o));
+    if (o->precond != SEM_PRECOND_JACOBI || o->proj_dim != 0 || o->timers != 0) {
+        set_error("sem_pcg_solve_noalloc: Jacobi preconditioner only, without projection or timers");
+        return SEM_EINVAL;
+    }
+    if (h->lv[0].nL > kNoAllocMaxLocal) {
+        set_error("sem_pcg_solve_noalloc: %lld local points exceed the limit of %lld (%d MiB scratch)",
+                  (long long)h->lv[0].nL, (long long)kNoAllocMaxLocal, SEM_NOALLOC_SCRATCH_MIB);
+        return SEM_EINVAL;
+    }
+    int dev = -1;
+    SEM_HIP(hipGetDevice(&dev));
+    if (dev != h->device) {
+        set_error("sem_pcg_solve_noalloc: current device %d is not the handle's device %d", dev, h->device);
+        return SEM_EINVAL;
+    }
+    return pcg_solve_noalloc(h, b, x, o, st, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -25,6 +25,8 @@ SEM_SMOOTH_JACOBI, SEM_SMOOTH_ASM, SEM_SMOOTH_RAS = 0, 1, 2
 SEM_ADVECT_AUTO, SEM_ADVECT_2D, SEM_ADVECT_3D = 0, 1, 2
 SEM_MAX_RHS = 4
 SEM_MAX_PROJ = 16
+# largest level-0 L-vector of sem_pcg_solve_noalloc (its static scratch)
+SEM_NOALLOC_MAX_LOCAL = 3142880
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 
@@ -108,6 +110,8 @@ _SIGS = {
     "sem_advect": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP, ctypes.c_int64, _VP, ctypes.c_int64, _VP]),
     "sem_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(SemSolveOpts),
                                      ctypes.POINTER(SemSolveStats), _VP]),
+    "sem_pcg_solve_noalloc": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(SemSolveOpts),
+                                             ctypes.POINTER(SemSolveStats), _VP]),
     "sem_grad_k": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
     "sem_rhs": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "sem_adjoint": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(SemSolveOpts), _VP, _VP, _VP,
@@ -437,6 +441,21 @@ class Sem:
                                  ctypes.byref(st), _stream())
         if raise_on_error and rc not in (SEM_OK, SEM_ENOCONV):
             _check(rc, "sem_pcg_solve")
+        return x, st.as_dict(), rc
+
+    def solve_noalloc(self, b, x, raise_on_error=True, **kw):
+        """sem_pcg_solve_noalloc: the Jacobi-PCG of solve() with every buffer
+        beyond b and x in the library's static device scratch (x is caller
+        storage: the initial guess unless zero_guess, then the solution).
+        Returns (x, stats dict, status)."""
+        torch = _torch()
+        o = self._opts(kw)
+        st = SemSolveStats()
+        rc = lib().sem_pcg_solve_noalloc(self._handle(), _dev_ptr(b, torch.float64, self.n_local, "b"),
+                                         _dev_ptr(x, torch.float64, self.n_local, "x"), ctypes.byref(o),
+                                         ctypes.byref(st), _stream())
+        if raise_on_error and rc not in (SEM_OK, SEM_ENOCONV):
+            _check(rc, "sem_pcg_solve_noalloc")
         return x, st.as_dict(), rc
 
     def smoother_apply(self, level, r, z=None, smoother="asm", h1=1.0, h2=0.0):

@@ -126,3 +126,11 @@ def test_default_solver_options():
     assert (o.coarse_tol, o.coarse_maxit) == (1e-2, 20)
     assert (o.cheb_lo, o.cheb_hi, o.zero_guess, o.proj_dim) == (0.1, 1.1, 1, 0)
     assert (o.smoother, o.use_graphs) == (S.SEM_SMOOTH_JACOBI, 0)
+
+
+def test_binding_constants_match_header():
+    """The limits the binding states are the header's."""
+    txt = open(HEADER).read()
+    for name in ("SEM_MAX_RHS", "SEM_MAX_PROJ", "SEM_NOALLOC_MAX_LOCAL"):
+        m = re.search(r"#define\s+" + name + r"\s+(\d+)", txt)
+        assert m and int(m.group(1)) == getattr(S, name), name
