@@ -12,6 +12,7 @@
 // without a host round trip per iteration.
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <initializer_list>
 #include <cmath>
 #include <mutex>
@@ -444,8 +445,10 @@ __global__ void dot_zw_kernel(int64_t n, VSet vs, int64_t ld, const KrylovScalar
 
 // Polak-Ribiere direction update, beta = (z_new, r_new - r_old) / (z_old, r_old)
 // = -alpha (z_new, A p) / rz_old (r_new - r_old = -alpha A p), taken by every
-// block from the partials of dot_zw_kernel; first = 1 gives p = z.  z is the
-// FP32 V-cycle output, zero on Dirichlet copies (mask W32 > 0).
+// block from the partials of dot_zw_kernel; first = 1 gives p = z without
+// reading p (on the first iteration p is uninitialised memory, and a 0 * p
+// term would turn any NaN bit pattern it holds into a NaN direction).  z is
+// the FP32 V-cycle output, zero on Dirichlet copies (mask W32 > 0).
 template <bool PAIR>
 __global__ void fcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars *sc, int parity,
                                    const double *__restrict__ pz, int64_t pst, int64_t nbz,
@@ -476,16 +479,22 @@ __global__ void fcg_p_fused_kernel(int64_t n, VSet vs, int64_t ld, KrylovScalars
     if constexpr (PAIR) {
         GRID_LOOP(g, n >> 1) {
             float zz[2], wt[2];
-            double pp[2];
+            double pp[2] = {0.0, 0.0};
             ld2(z, g, zz);
             ld2(W32, g, wt);
-            ld2(p, g, pp);
+            if (!first) ld2(p, g, pp);
 #pragma unroll
-            for (int k = 0; k < 2; ++k) pp[k] = (wt[k] > 0.0f ? (double)zz[k] : 0.0) + be * pp[k];
+            for (int k = 0; k < 2; ++k) {
+                const double zk = wt[k] > 0.0f ? (double)zz[k] : 0.0;
+                pp[k] = first ? zk : zk + be * pp[k];
+            }
             st2(p, g, pp);
         }
     } else {
-        GRID_LOOP(i, n) p[i] = (W32[i] > 0.0f ? (double)z[i] : 0.0) + be * p[i];
+        GRID_LOOP(i, n) {
+            const double zi = W32[i] > 0.0f ? (double)z[i] : 0.0;
+            p[i] = first ? zi : zi + be * p[i];
+        }
     }
 }
 
@@ -731,13 +740,12 @@ __global__ void sqrtd_axpby_kernel(int64_t n, const double *__restrict__ Dinv,
         y[i] = a * sqrt(Dinv[i]) * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
 }
 
-// y = a x + b y
-__global__ void axpby_kernel(int64_t n, const double *__restrict__ x, double a, double b,
-                             double *__restrict__ y)
+// y = a x + b y (y not read when b = 0; x may be y)
+__global__ void axpby_kernel(int64_t n, const double *x, double a, double b, double *y)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        y[i] = a * x[i] + b * y[i];
+        y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
 }
 
 // ============================================================== host side
@@ -772,6 +780,18 @@ __global__ void axpby_kernel(int64_t n, const double *__restrict__ x, double a, 
 // stride, in ints, between the `done` flags of consecutive KrylovScalars
 constexpr int kScStride = (int)(sizeof(KrylovScalars) / sizeof(int));
 static_assert(sizeof(KrylovScalars) % sizeof(int) == 0, "KrylovScalars size");
+
+// Solver workspace allocation.  With SEM_POISON_WORKSPACE set to a nonzero
+// value in the environment, every new buffer is filled with 0xFF bytes (NaN
+// as FP32 and FP64), so that a kernel reading workspace it has not written
+// shows up as NaN instead of depending on what the memory held before.
+static int ws_alloc(void **p, size_t bytes)
+{
+    SEM_HIP(hipMalloc(p, bytes));
+    const char *e = std::getenv("SEM_POISON_WORKSPACE");
+    if (e && std::atoi(e) != 0) SEM_HIP(hipMemset(*p, 0xFF, bytes));
+    return SEM_OK;
+}
 
 static void free_vectors(Workspace &w)
 {
@@ -891,12 +911,12 @@ static int ensure_workspace(sem_handle h, bool pmg, int nv)
         // vector-kernel partials: at most kMaxRedBlocks records of 3 per
         // vector; operator partials: one per workgroup of the persistent grid
         w.pst = 3 * kMaxRedBlocks;
-        SEM_HIP(hipMalloc(&w.partial, sizeof(double) * std::max<int64_t>(w.pst * kMaxRhs,
+        SEM_TRY(ws_alloc((void **)&w.partial, sizeof(double) * std::max<int64_t>(w.pst * kMaxRhs,
                                                                          (int64_t)kMaxProj * kMaxRedBlocks)));
         w.pst_ax = (int64_t)(F.n_cu > 0 ? F.n_cu : 256) * kAxMaxBlocksPerCU + 64;
-        SEM_HIP(hipMalloc(&w.partial_ax, sizeof(double) * w.pst_ax * kMaxRhs));
-        SEM_HIP(hipMalloc(&w.sc, sizeof(KrylovScalars) * kMaxRhs));
-        SEM_HIP(hipMalloc(&w.sc_c, sizeof(KrylovScalars) * kMaxRhs));
+        SEM_TRY(ws_alloc((void **)&w.partial_ax, sizeof(double) * w.pst_ax * kMaxRhs));
+        SEM_TRY(ws_alloc((void **)&w.sc, sizeof(KrylovScalars) * kMaxRhs));
+        SEM_TRY(ws_alloc((void **)&w.sc_c, sizeof(KrylovScalars) * kMaxRhs));
         SEM_HIP(hipHostMalloc((void **)&w.host_sc, 2 * kMaxRhs * sizeof(KrylovScalars),
                               hipHostMallocDefault));
     }
@@ -905,35 +925,35 @@ static int ensure_workspace(sem_handle h, bool pmg, int nv)
         const bool pm = pmg || w.pmg;
         free_vectors(w);
         const int64_t n = F.nL;
-        SEM_HIP(hipMalloc(&w.r, sizeof(double) * n * nvn));
-        SEM_HIP(hipMalloc(&w.p, sizeof(double) * n * nvn));
-        SEM_HIP(hipMalloc(&w.w, sizeof(double) * n * nvn));
-        SEM_HIP(hipMalloc(&w.z, sizeof(double) * n * nvn));
+        SEM_TRY(ws_alloc((void **)&w.r, sizeof(double) * n * nvn));
+        SEM_TRY(ws_alloc((void **)&w.p, sizeof(double) * n * nvn));
+        SEM_TRY(ws_alloc((void **)&w.w, sizeof(double) * n * nvn));
+        SEM_TRY(ws_alloc((void **)&w.z, sizeof(double) * n * nvn));
         if (pm) {
             for (int l = 0; l + 1 < h->n_levels; ++l) {
                 const int64_t m = h->lv[l].nL * nvn;
-                SEM_HIP(hipMalloc(&w.mg_r[l], sizeof(float) * m));
-                SEM_HIP(hipMalloc(&w.mg_x[l], sizeof(float) * m));
-                SEM_HIP(hipMalloc(&w.mg_t[l], sizeof(float) * m));
-                SEM_HIP(hipMalloc(&w.mg_d[l], sizeof(float) * m));
+                SEM_TRY(ws_alloc((void **)&w.mg_r[l], sizeof(float) * m));
+                SEM_TRY(ws_alloc((void **)&w.mg_x[l], sizeof(float) * m));
+                SEM_TRY(ws_alloc((void **)&w.mg_t[l], sizeof(float) * m));
+                SEM_TRY(ws_alloc((void **)&w.mg_d[l], sizeof(float) * m));
                 if (h->lv[l].nq > 8)  // unfused transfers stage the residual here
-                    SEM_HIP(hipMalloc(&w.mg_s[l], sizeof(float) * m));
+                    SEM_TRY(ws_alloc((void **)&w.mg_s[l], sizeof(float) * m));
             }
             const int lc = h->n_levels - 1;
             const int64_t m = h->lv[lc].nL * nvn;
-            SEM_HIP(hipMalloc(&w.mg_r[lc], sizeof(double) * m));  // coarse rhs
-            SEM_HIP(hipMalloc(&w.mg_x[lc], sizeof(double) * m));  // coarse solution
-            SEM_HIP(hipMalloc(&w.c_r, sizeof(double) * m));
-            SEM_HIP(hipMalloc(&w.c_p, sizeof(double) * m));
-            SEM_HIP(hipMalloc(&w.c_w, sizeof(double) * m));
+            SEM_TRY(ws_alloc((void **)&w.mg_r[lc], sizeof(double) * m));  // coarse rhs
+            SEM_TRY(ws_alloc((void **)&w.mg_x[lc], sizeof(double) * m));  // coarse solution
+            SEM_TRY(ws_alloc((void **)&w.c_r, sizeof(double) * m));
+            SEM_TRY(ws_alloc((void **)&w.c_p, sizeof(double) * m));
+            SEM_TRY(ws_alloc((void **)&w.c_w, sizeof(double) * m));
         }
         w.nv = nvn;
         w.pmg = pm;
     }
     for (int l = 0; l < h->n_levels; ++l) {
         Level &L = h->lv[l];
-        if (!L.Dinv) SEM_HIP(hipMalloc(&L.Dinv, sizeof(double) * L.nL));
-        if (pmg && l < h->n_levels - 1 && !L.Dinv32) SEM_HIP(hipMalloc(&L.Dinv32, sizeof(float) * L.nL));
+        if (!L.Dinv) SEM_TRY(ws_alloc((void **)&L.Dinv, sizeof(double) * L.nL));
+        if (pmg && l < h->n_levels - 1 && !L.Dinv32) SEM_TRY(ws_alloc((void **)&L.Dinv32, sizeof(float) * L.nL));
     }
     return SEM_OK;
 }
@@ -1138,8 +1158,8 @@ static int ensure_schwarz_ws(sem_handle h, int nv)
     }
     const int nvn = std::max(nv, w.sz_nv);
     ulen = std::max(ulen, w.sz_U_len);
-    SEM_HIP(hipMalloc(&w.sz_U, sizeof(float) * ulen * nvn));
-    for (int l = 0; l < ns; ++l) SEM_HIP(hipMalloc(&w.sz_acc[l], sizeof(float) * h->lv[l].nL * nvn));
+    SEM_TRY(ws_alloc((void **)&w.sz_U, sizeof(float) * ulen * nvn));
+    for (int l = 0; l < ns; ++l) SEM_TRY(ws_alloc((void **)&w.sz_acc[l], sizeof(float) * h->lv[l].nL * nvn));
     w.sz_U_len = ulen;
     w.sz_nv = nvn;
     return SEM_OK;
@@ -1550,15 +1570,15 @@ static int ensure_projection(sem_handle h, int nv, int L, double h1, double h2)
         w.proj_h2 = h2;
     }
     for (int v = 0; v < nv; ++v) {
-        if (!w.proj[v].xt) SEM_HIP(hipMalloc(&w.proj[v].xt, sizeof(double) * n * L));
-        if (!w.proj[v].bt) SEM_HIP(hipMalloc(&w.proj[v].bt, sizeof(double) * n * L));
+        if (!w.proj[v].xt) SEM_TRY(ws_alloc((void **)&w.proj[v].xt, sizeof(double) * n * L));
+        if (!w.proj[v].bt) SEM_TRY(ws_alloc((void **)&w.proj[v].bt, sizeof(double) * n * L));
     }
     if (w.proj_nv < nv) {
         if (w.proj_xb) (void)hipFree(w.proj_xb);
         if (w.proj_bp) (void)hipFree(w.proj_bp);
         w.proj_xb = w.proj_bp = nullptr;
-        SEM_HIP(hipMalloc(&w.proj_xb, sizeof(double) * n * nv));
-        SEM_HIP(hipMalloc(&w.proj_bp, sizeof(double) * n * nv));
+        SEM_TRY(ws_alloc((void **)&w.proj_xb, sizeof(double) * n * nv));
+        SEM_TRY(ws_alloc((void **)&w.proj_bp, sizeof(double) * n * nv));
         w.proj_nv = nv;
     }
     return SEM_OK;
@@ -1906,7 +1926,7 @@ int adjoint(sem_handle h, const double *u, const double *g, const sem_solve_opts
     const Level &F = h->lv[0];
     const int64_t n = F.nL;
     SEM_TRY(ensure_workspace(h, false, 1));
-    if (!h->ws.aux) SEM_HIP(hipMalloc(&h->ws.aux, sizeof(double) * n));
+    if (!h->ws.aux) SEM_TRY(ws_alloc((void **)&h->ws.aux, sizeof(double) * n));
     // right-hand side R QQ^T g in a workspace vector the solver does not touch
     double *rhs = h->ws.aux;
     SEM_HIP(hipMemcpyAsync(rhs, g, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -2154,7 +2174,7 @@ int sem_smoother_apply(sem_handle h, int level, int smoother, double h1, double 
         w.sz_U = nullptr;
         const int nvn = std::max(1, w.sz_nv);
         const int64_t len = std::max<int64_t>(ulen, w.sz_U_len);
-        SEM_HIP(hipMalloc(&w.sz_U, sizeof(float) * len * nvn));
+        SEM_TRY(ws_alloc((void **)&w.sz_U, sizeof(float) * len * nvn));
         w.sz_U_len = len;
         w.sz_nv = nvn;
     }

@@ -300,6 +300,49 @@ def test_pmg_fcg_reaches_1e8_and_matches_oracle():
     s.free()
 
 
+@pytest.fixture
+def poisoned_workspace(monkeypatch):
+    """New solver workspace filled with 0xFF bytes (NaN as FP32 and FP64)."""
+    monkeypatch.setenv("SEM_POISON_WORKSPACE", "1")
+    yield
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "asm", "ras"])
+def test_solves_never_read_unwritten_workspace(smoother, poisoned_workspace):
+    """Regression: the first flexible-CG direction p = z must not read p.
+    It used to be formed as z + 0 * p with p fresh workspace, so NaN bit
+    patterns left in that memory (e.g. the -1 entries of a freed index
+    array) made (p, A p) NaN and the solve break down at its first
+    iteration, depending on where the allocator placed p.  With every new
+    workspace buffer filled with NaN bytes, single and lockstep p-MG solves
+    with each smoother, Jacobi-PCG and a projected sequence all converge to
+    finite solutions equal to those on ordinary memory."""
+    print(f"[gpu] solves on NaN-filled workspace, {smoother}", flush=True)
+    N, shape = 7, (4, 4, 4)
+    m = _mesh(shape, N, deform="cyclic")
+    lv = solvers.Level(N, m.x, m.y, m.z, m.gid, m.dirichlet, 1.0, 10.0)
+    b = lv.rhs(inputs.gaussian_per_node(m.gid, 30))
+    B = np.stack([b, lv.rhs(inputs.gaussian_per_node(m.gid, 31))])
+    kw = dict(tol=1e-8, h1=1.0, h2=10.0, precond="pmg", smoother=smoother)
+    if smoother != "jacobi":
+        kw["cheb_lo"] = 0.25
+    s = Sem(m, levels=(7, 3, 1))
+    x1, st1, rc1 = s.solve(_dev(b), **kw)
+    X, sts, rc = s.solve_multi(_dev(B), **kw)
+    xj, stj, rcj = s.solve(_dev(b), tol=1e-8, h1=1.0, h2=10.0, precond="jacobi", maxit=5000)
+    for q, r_ in ((st1, rc1), (sts[0], rc), (sts[1], rc), (stj, rcj)):
+        assert r_ == 0 and q["converged"] and q["true_rel_res"] <= 1.5e-8, q
+    for t in (x1, X, xj):
+        assert bool(torch.isfinite(t).all())
+    assert torch.equal(X[0], x1)
+    if smoother == "jacobi":
+        for k in range(3):
+            xp, stp, rcp = s.solve(_dev(b * (1.0 + 0.1 * k)), tol=1e-8, h1=1.0, h2=10.0,
+                                   precond="pmg", proj_dim=4)
+            assert rcp == 0 and stp["true_rel_res"] <= 1.5e-8 and bool(torch.isfinite(xp).all())
+    s.free()
+
+
 def test_grad_k_parity():
     print("[gpu] grad_k", flush=True)
     N = 7
