@@ -192,11 +192,12 @@ typedef struct {
                             1 / (subdomains containing the node); needs N >= 2 on every
                             smoothed level and a conforming hex mesh; the Chebyshev
                             interval uses the power-method lambda_max of M^{-1} A */
-    int use_graphs;      /* must be 0 (kernels launched one by one).  1 would replay each
-                            V-cycle of the outer FCG from a captured HIP graph; that
-                            path is switched off (SEM_EINVAL) because one replay was
-                            seen to differ from the kernel-by-kernel solve with no
-                            cause found. */
+    int use_graphs;      /* PMG: 1 replays each V-cycle of the outer FCG from a HIP graph
+                            captured once per set of unconverged right-hand sides and
+                            state (recaptured when a pointer or value its kernels take
+                            changes); the iterates equal those of 0 (kernels launched
+                            one by one, the default) bit for bit.  No effect with
+                            Jacobi. */
     int timers;          /* 1: time the solver's phases with HIP events on `stream` (fills
                             the ms_ax .. ms_coarse fields of the stats); adds event records
                             between kernels and no host synchronisation.  0: off (fields 0) */
@@ -260,7 +261,8 @@ SEM_API int sem_pcg_solve(sem_handle h, const double *b, double *x, const sem_so
  * use on that GPU until the process ends.  b, x, opts, stats and the stream as
  * for sem_pcg_solve; the iterates, solution and stats equal sem_pcg_solve's
  * with the Jacobi preconditioner.
- *   Limits: opts->precond = SEM_PRECOND_JACOBI, proj_dim = 0, timers = 0, and
+ *   Limits: opts->precond = SEM_PRECOND_JACOBI, proj_dim = 0, timers = 0,
+ *   use_graphs = 0, and
  *   n_local <= SEM_NOALLOC_MAX_LOCAL, else SEM_EINVAL with nothing enqueued;
  *   the current device must be the handle's.
  *   Calls no hipMalloc/hipFree (nor any allocating library routine); the

@@ -24,7 +24,7 @@ static void free_level(Level &L)
 {
     free_schwarz(L);
     void *ptrs[] = {L.G, L.B, L.G32, L.B32, L.W, L.W32, L.gid, L.dir, L.perm, L.offs,
-                    L.chunk_b, L.chunk_e, L.chunk_mask, L.over,
+                    L.chunk_perm, L.over,
                     L.D, L.D32, L.Jc, L.Jc32, L.Dinv, L.Dinv32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);

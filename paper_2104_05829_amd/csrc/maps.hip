@@ -201,56 +201,48 @@ int build_maps(Level &L, const int64_t *gid, const uint8_t *dir, const double *x
 }
 
 // Pack whole segments, in canonical order, into chunks of at most 64 copies
-// (one wavefront each): chunk c covers perm[cstart[c] .. cstart[c+1]) and
-// bit l of cmask[c] marks lane l as the first copy of a segment.  Segments
-// with more than 64 copies go to an overflow list handled one thread per
-// segment.  Greedy on the host: O(segments), setup only.
+// (one wavefront each), and write each chunk's copy list padded to 64 lanes:
+// chunk_perm[c][l] = copy l of the chunk, with kGsSegStart set where it
+// starts a segment, -1 past the chunk's end.  Segments with more than 64
+// copies go to an overflow list handled one thread per segment.  On the host:
+// O(shared copies), setup only.
 int build_gs_chunks(Level &L, hipStream_t s)
 {
+    if (L.nL >= (int64_t)kGsSegStart) {  // copy indices share their word with the flag
+        set_error("setup: %lld local points exceed the gather-scatter limit of 2^30", (long long)L.nL);
+        return SEM_EINVAL;
+    }
     std::vector<int32_t> offs(L.nseg + 1);
     if (L.nseg > 0)
         SEM_HIP(hipMemcpy(offs.data(), L.offs, sizeof(int32_t) * (L.nseg + 1), hipMemcpyDeviceToHost));
     else
         offs[0] = 0;
-    std::vector<int32_t> cb, ce;
-    std::vector<uint64_t> cmask;
+    std::vector<int32_t> perm(L.ncopies);
+    if (L.ncopies > 0)
+        SEM_HIP(hipMemcpy(perm.data(), L.perm, sizeof(int32_t) * L.ncopies, hipMemcpyDeviceToHost));
+    std::vector<int32_t> cp;  // padded chunk lists
     std::vector<int32_t> over;
-    int32_t cur = -1, used = 0;
-    uint64_t mask = 0;
+    int32_t used = 64;  // lanes filled in the open chunk (64: none open)
     for (int64_t q = 0; q < L.nseg; ++q) {
         const int32_t a = offs[q], len = offs[q + 1] - offs[q];
         if (len > 64) {
             over.push_back((int32_t)q);
             continue;
         }
-        if (cur < 0 || used + len > 64 || a != cur + used) {
-            if (cur >= 0) {
-                cb.push_back(cur);
-                ce.push_back(cur + used);
-                cmask.push_back(mask);
-            }
-            cur = a;
+        if (used + len > 64) {  // open a new chunk
+            cp.resize(cp.size() + 64, -1);
             used = 0;
-            mask = 0;
         }
-        mask |= 1ULL << used;
+        int32_t *lanes = cp.data() + cp.size() - 64;
+        for (int32_t o = 0; o < len; ++o) lanes[used + o] = perm[a + o] | (o == 0 ? kGsSegStart : 0);
         used += len;
     }
-    if (cur >= 0) {
-        cb.push_back(cur);
-        ce.push_back(cur + used);
-        cmask.push_back(mask);
-    }
-    const int64_t nch = (int64_t)cmask.size();
+    const int64_t nch = (int64_t)cp.size() / 64;
     L.nchunks = nch;
     L.nover = (int64_t)over.size();
     if (nch > 0) {
-        SEM_HIP(hipMalloc(&L.chunk_b, sizeof(int32_t) * nch));
-        SEM_HIP(hipMalloc(&L.chunk_e, sizeof(int32_t) * nch));
-        SEM_HIP(hipMalloc(&L.chunk_mask, sizeof(uint64_t) * nch));
-        SEM_HIP(hipMemcpy(L.chunk_b, cb.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice));
-        SEM_HIP(hipMemcpy(L.chunk_e, ce.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice));
-        SEM_HIP(hipMemcpy(L.chunk_mask, cmask.data(), sizeof(uint64_t) * nch, hipMemcpyHostToDevice));
+        SEM_HIP(hipMalloc(&L.chunk_perm, sizeof(int32_t) * cp.size()));
+        SEM_HIP(hipMemcpy(L.chunk_perm, cp.data(), sizeof(int32_t) * cp.size(), hipMemcpyHostToDevice));
     }
     if (L.nover > 0) {
         SEM_HIP(hipMalloc(&L.over, sizeof(int32_t) * L.nover));

@@ -7,8 +7,8 @@ namespace semx {
 // QQ^T (Sec. 2.3 eq. (dssum); gs_op(+) of Sec. 3.2) as a segmented reduction
 // over the sorted maps.  The shared copies (perm, canonical order) are packed
 // into chunks of whole segments of at most 64 copies; one 64-lane wavefront
-// takes one chunk: lane l loads copy l (coalesced perm load, one gathered
-// value), then sums the lanes of its segment in ascending order by cross-lane
+// takes one chunk: lane l loads copy l (one coalesced load of the chunk's
+// padded copy list, one gathered value), then sums the lanes of its segment in ascending order by cross-lane
 // reads and writes the total back.  Each sum starts from 0 and adds the
 // copies in ascending local index order, so the result is bit-identical to a
 // sequential pass.  Unshared copies are never touched.  Segments with more
@@ -28,13 +28,15 @@ __device__ inline int64_t xcd_chunk_block(int64_t b, int64_t nb)
 
 constexpr int kGsWavesPerBlock = 4;
 
-// The maps of a chunk (perm slice, segment-start mask) are loaded once and
-// applied to every vector of the batch in turn.
+// One map load per lane ahead of the values: the chunk's copy list padded to
+// 64 lanes (cperm[c][lane]: the copy, with kGsSegStart set where it starts a
+// segment, or -1 past the chunk's end), so the gathers depend on a single
+// coalesced load; the chunk size and the segment starts follow by ballots.
+// The copy indices are applied to every vector of the batch in turn.
 template <typename T>
 __global__ void __launch_bounds__(64 * kGsWavesPerBlock)
-gs_chunk_kernel(int64_t nchunks, const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
-                const uint64_t *__restrict__ cmask, const int32_t *__restrict__ perm,
-                T *__restrict__ v, int64_t ld, VSet vs, const int *__restrict__ skip, int skip_stride)
+gs_chunk_kernel(int64_t nchunks, const int32_t *__restrict__ cperm, T *__restrict__ v, int64_t ld,
+                VSet vs, const int *__restrict__ skip, int skip_stride)
 {
     uint32_t pack;
     const int na = live_vectors(vs, skip, skip_stride, &pack);
@@ -42,11 +44,17 @@ gs_chunk_kernel(int64_t nchunks, const int32_t *__restrict__ cb, const int32_t *
     const int lane = threadIdx.x & 63;
     const int64_t c = xcd_chunk_block(blockIdx.x, gridDim.x) * kGsWavesPerBlock + (threadIdx.x >> 6);
     if (c >= nchunks) return;  // uniform per wavefront
-    const int b = cb[c];
-    const int cnt = ce[c] - b;
-    const bool act = lane < cnt;
-    const int idx = act ? perm[b + lane] : 0;
-    const uint64_t m = cmask[c];  // bit l: lane l starts a segment (bit 0 always set)
+    const int ent = cperm[c * 64 + lane];
+    const bool act = ent >= 0;
+    const int idx = act ? (ent & (kGsSegStart - 1)) : 0;
+    // the gathers of every live vector are issued before the first sum so
+    // their latencies overlap; each vector's sum is the same as alone
+    T val[kMaxRhs];
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q)
+        val[q] = (q < na && act) ? v[(int64_t)((pack >> (8 * q)) & 255u) * ld + idx] : T(0);
+    const uint64_t m = __ballot(act && (ent & kGsSegStart));  // bit l: lane l starts a segment
+    const int cnt = __popcll(__ballot(act));  // the chunk's copies are lanes 0 .. cnt-1
     const uint64_t upto = (lane == 63) ? ~0ULL : ((2ULL << lane) - 1ULL);
     const int s0 = 63 - __clzll((long long)(m & upto));      // first lane of my segment
     const uint64_t above = m & ~upto;
@@ -55,12 +63,6 @@ gs_chunk_kernel(int64_t nchunks, const int32_t *__restrict__ cb, const int32_t *
     int maxlen = len;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o));
-    // the gathers of every live vector are issued before the first sum so
-    // their latencies overlap; each vector's sum is the same as alone
-    T val[kMaxRhs];
-#pragma unroll
-    for (int q = 0; q < kMaxRhs; ++q)
-        val[q] = (q < na && act) ? v[(int64_t)((pack >> (8 * q)) & 255u) * ld + idx] : T(0);
 #pragma unroll
     for (int q = 0; q < kMaxRhs; ++q) {
         if (q >= na) break;
@@ -102,8 +104,7 @@ int launch_gs_multi(const Level &L, T *v, int64_t ld, const VSet &vs, hipStream_
     if (L.nchunks > 0) {
         const int64_t nb = (L.nchunks + kGsWavesPerBlock - 1) / kGsWavesPerBlock;
         hipLaunchKernelGGL(gs_chunk_kernel<T>, dim3((unsigned)nb), dim3(64 * kGsWavesPerBlock), 0, s,
-                           L.nchunks, L.chunk_b, L.chunk_e, L.chunk_mask, L.perm, v, ld, vs, skip,
-                           skip_stride);
+                           L.nchunks, L.chunk_perm, v, ld, vs, skip, skip_stride);
         SEM_HIP(hipGetLastError());
     }
     if (L.nover > 0) {

@@ -30,6 +30,8 @@ void set_error(const char *fmt, ...);
     } while (0)
 
 constexpr int kMaxN = 15;
+// flag bit of a chunk lane's copy index: the copy starts a segment
+constexpr int32_t kGsSegStart = 1 << 30;
 // largest Gauss rule of the dealiased advection operator (M^2 threads per element)
 constexpr int kMaxGauss = 16;
 // largest number of workgroups per CU of the persistent element-operator grid
@@ -118,8 +120,9 @@ struct Level {
     int32_t *perm = nullptr, *offs = nullptr;
     // wavefront chunks of whole segments for the gather-scatter kernel
     int64_t nchunks = 0, nover = 0;
-    int32_t *chunk_b = nullptr, *chunk_e = nullptr;  // perm range of each chunk
-    uint64_t *chunk_mask = nullptr;                   // segment-start lanes
+    // [nchunks][64] copy of each lane (perm order), | kGsSegStart where it
+    // starts a segment, -1 past the chunk's end
+    int32_t *chunk_perm = nullptr;
     int32_t *over = nullptr;                          // segments longer than 64 copies
     double *D = nullptr;   // Dh [nq][nq] (row = point)
     float *D32 = nullptr;

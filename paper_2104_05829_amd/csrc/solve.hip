@@ -1436,7 +1436,7 @@ static uint64_t vcycle_sig(sem_handle h, const VSet &vs, const SolveCfg &cfg)
         const Level &L = h->lv[l];
         const void *lp[] = {w.mg_r[l], w.mg_x[l], w.mg_t[l], w.mg_d[l], w.mg_s[l], w.sz_acc[l],
                             L.G, L.B, L.G32, L.B32, L.D, L.D32, L.W, L.W32, L.Jc, L.Jc32, L.Dinv,
-                            L.Dinv32, L.chunk_b, L.chunk_e, L.chunk_mask, L.over, L.perm, L.offs, L.sz_ix, L.sz_S, L.sz_lam,
+                            L.Dinv32, L.chunk_perm, L.over, L.perm, L.offs, L.sz_ix, L.sz_S, L.sz_lam,
                             L.sz_rc, L.sz_off, L.sz_src, L.sz_w};
         for (const void *p : lp) f.add(p);
         f.add(L.lmax);
@@ -2207,13 +2207,6 @@ static int check_solve_opts(const char *who, const sem_solve_opts *o)
         set_error("%s: bad smoother %d", who, o->smoother);
         return SEM_EINVAL;
     }
-    if (o->use_graphs != 0) {
-        // switched off: in one test run a solve whose V-cycles were replayed
-        // from captured graphs differed from the same solve launched kernel
-        // by kernel, and no cause was found in this library
-        set_error("%s: use_graphs: V-cycle graph replay is switched off", who);
-        return SEM_EINVAL;
-    }
     if (o->proj_dim < 0 || o->proj_dim > kMaxProj) {
         set_error("%s: proj_dim = %d outside 0..%d", who, o->proj_dim, kMaxProj);
         return SEM_EINVAL;
@@ -2265,8 +2258,8 @@ int sem_pcg_solve_noalloc(sem_handle h, const double *b, double *x, const sem_so
         return SEM_EINVAL;
     }
     SEM_TRY(check_solve_opts("sem_pcg_solve_noalloc", o));
-    if (o->precond != SEM_PRECOND_JACOBI || o->proj_dim != 0 || o->timers != 0) {
-        set_error("sem_pcg_solve_noalloc: Jacobi preconditioner only, without projection or timers");
+    if (o->precond != SEM_PRECOND_JACOBI || o->proj_dim != 0 || o->timers != 0 || o->use_graphs != 0) {
+        set_error("sem_pcg_solve_noalloc: Jacobi preconditioner only, without projection, timers or graphs");
         return SEM_EINVAL;
     }
     if (h->lv[0].nL > kNoAllocMaxLocal) {

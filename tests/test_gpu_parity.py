@@ -335,6 +335,8 @@ def test_solves_never_read_unwritten_workspace(smoother, poisoned_workspace):
     for t in (x1, X, xj):
         assert bool(torch.isfinite(t).all())
     assert torch.equal(X[0], x1)
+    xg, stg, rcg = s.solve(_dev(b), use_graphs=1, **kw)  # V-cycles replayed from graphs
+    assert rcg == 0 and stg["iters"] == st1["iters"] and torch.equal(xg, x1)
     if smoother == "jacobi":
         for k in range(3):
             xp, stp, rcp = s.solve(_dev(b * (1.0 + 0.1 * k)), tol=1e-8, h1=1.0, h2=10.0,
