@@ -185,17 +185,34 @@ def box_mesh(ex, ey, ez, N, **kw) -> inputs.BoxMesh:
     return inputs.box_mesh(ex, ey, ez, xi, **kw)
 
 
+_T = None
+_RAW_STREAM = None
+
+
 def _torch():
-    import torch
-    return torch
+    global _T
+    if _T is None:
+        import torch
+        _T = torch
+    return _T
 
 
 def _stream():
+    """Raw pointer (an int) of torch's current HIP stream on the current device."""
+    global _RAW_STREAM
     torch = _torch()
-    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if _RAW_STREAM is None:
+        C = torch._C
+        if hasattr(C, "_cuda_getCurrentRawStream") and hasattr(C, "_cuda_getDevice"):
+            _RAW_STREAM = lambda: C._cuda_getCurrentRawStream(C._cuda_getDevice())  # noqa: E731
+        else:
+            _RAW_STREAM = lambda: torch.cuda.current_stream().cuda_stream  # noqa: E731
+    return _RAW_STREAM()
 
 
 def _dev_ptr(t, dtype, n, name):
+    """Device address of tensor t after checking its placement, dtype,
+    layout and size (a plain int, passed as a void pointer)."""
     torch = _torch()
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
@@ -207,7 +224,7 @@ def _dev_ptr(t, dtype, n, name):
         raise ValueError(f"{name} must be contiguous")
     if n is not None and t.numel() != n:
         raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
-    return ctypes.c_void_p(t.data_ptr())
+    return t.data_ptr()
 
 
 def _dev_batch(t, dtype, n, name):
@@ -395,7 +412,7 @@ class Sem:
                 raise TypeError(f"unknown solver option {name}")
             setattr(o, name, val)
         if kk is not None:
-            o.k = _dev_ptr(kk, torch.float64, self.n_local, "k").value
+            o.k = _dev_ptr(kk, torch.float64, self.n_local, "k")
         return o
 
     def rhs(self, f, out=None):
