@@ -460,7 +460,8 @@ int build_schwarz(Level &L, hipStream_t s)
 // element's S matrices and eigenvalues along c sit in LDS; the b and a
 // contractions run through two LDS buffers.  Own points are read directly and
 // written to acc; extension points are gathered through the compact map and
-// (ASM) written to U.  FP32.
+// (ASM) written to U.  The eigenbases and the extension map of an element are
+// loaded once and serve every vector of the batch in turn.  FP32.
 template <int NE>
 struct FdmShape {
     static constexpr int NQ = NE - 2, NE2 = NE * NE, THREADS = 256;
@@ -482,11 +483,6 @@ fdm_kernel(int64_t E, const int32_t *__restrict__ ix, const float *__restrict__ 
     __shared__ float slz[EPB][NE];
     __shared__ float sa[EPB][NE][NE][LDP];  // [c][b][a]
     __shared__ float sb[EPB][NE][NE][LDP];
-    const int64_t v = vs.at(blockIdx.y);
-    r += v * ld;
-    if (t) t += v * ld;
-    acc += v * ld;
-    if (EXT_OUT) U += v * E * NEXT;
     const int tid = threadIdx.x;
     const int el = tid / NE2, ij = tid - el * NE2;
     const int a = ij % NE, b = ij / NE;
@@ -500,7 +496,9 @@ fdm_kernel(int64_t E, const int32_t *__restrict__ ix, const float *__restrict__ 
         const int64_t e = g * EPB + el;
         const bool act = lane && e < E;
         __syncthreads();  // LDS of the previous group consumed
-        float vv[NE], w[NE];
+        // the element's eigenbases and eigenvalues and this column's
+        // extension copies, once for every vector of the batch
+        int32_t q[NE];
         float lxa = 1.0f, lyb = 1.0f;
         if (act) {
             const float *Se = Sg + e * 3 * NE2;
@@ -510,108 +508,122 @@ fdm_kernel(int64_t E, const int32_t *__restrict__ ix, const float *__restrict__ 
             lxa = lamg[e * 3 * NE + a];
             lyb = lamg[e * 3 * NE + NE + b];
             const int32_t *ixe = ix + e * NEXT;
-            auto gather = [&](int slot) {
-                const int32_t q = ixe[slot];
-                return q >= 0 ? (t ? r[q] - t[q] : r[q]) : 0.0f;
-            };
             if (acol) {
 #pragma unroll
-                for (int c = 0; c < NE; ++c) vv[c] = gather(ebase + c);
+                for (int c = 0; c < NE; ++c) q[c] = ixe[ebase + c];
             } else {
-                const float *re = r + e * NP + (b - 1) * NQ + (a - 1);
-                const float *te = t ? t + e * NP + (b - 1) * NQ + (a - 1) : nullptr;
-                vv[0] = gather(ebase);
-#pragma unroll
-                for (int c = 1; c < NE - 1; ++c)
-                    vv[c] = te ? re[(c - 1) * NQ * NQ] - te[(c - 1) * NQ * NQ] : re[(c - 1) * NQ * NQ];
-                vv[NE - 1] = gather(ebase + 1);
+                q[0] = ixe[ebase];
+                q[NE - 1] = ixe[ebase + 1];
             }
         }
-        __syncthreads();  // sSz, slz ready
-        if (act) {
-            // modes along c (rows of Sz read contiguously)
+        for (int f = 0; f < vs.n; ++f) {
+            const int64_t v = vs.at(f);
+            const float *rv = r + v * ld;
+            const float *tv = t ? t + v * ld : nullptr;
+            float vv[NE], w[NE];
+            if (act) {
+                auto gather = [&](int32_t qq) {
+                    return qq >= 0 ? (tv ? rv[qq] - tv[qq] : rv[qq]) : 0.0f;
+                };
+                if (acol) {
 #pragma unroll
-            for (int k = 0; k < NE; ++k) w[k] = 0.0f;
+                    for (int c = 0; c < NE; ++c) vv[c] = gather(q[c]);
+                } else {
+                    const float *re = rv + e * NP + (b - 1) * NQ + (a - 1);
+                    const float *te = tv ? tv + e * NP + (b - 1) * NQ + (a - 1) : nullptr;
+                    vv[0] = gather(q[0]);
 #pragma unroll
-            for (int c = 0; c < NE; ++c)
-#pragma unroll
-                for (int k = 0; k < NE; ++k) w[k] += sS[el][2][c][k] * vv[c];
-#pragma unroll
-            for (int k = 0; k < NE; ++k) sa[el][k][b][a] = w[k];
-        }
-        __syncthreads();
-        if (act) {
-            // modes along b (thread (a, j = b))
-            float Sm[NE];
-#pragma unroll
-            for (int m = 0; m < NE; ++m) Sm[m] = sS[el][1][m][b];
-#pragma unroll
-            for (int k = 0; k < NE; ++k) {
-                float s = 0.0f;
-#pragma unroll
-                for (int m = 0; m < NE; ++m) s += Sm[m] * sa[el][k][m][a];
-                sb[el][k][b][a] = s;
+                    for (int c = 1; c < NE - 1; ++c)
+                        vv[c] = te ? re[(c - 1) * NQ * NQ] - te[(c - 1) * NQ * NQ] : re[(c - 1) * NQ * NQ];
+                    vv[NE - 1] = gather(q[NE - 1]);
+                }
             }
-        }
-        __syncthreads();
-        if (act) {
-            // modes along a (thread (i = a, j = b)), scaled by the inverse eigenvalue sum
-            float Sm[NE];
+            __syncthreads();  // sS, slz ready; the previous vector's LDS consumed
+            if (act) {
+                // modes along c (rows of Sz read contiguously)
 #pragma unroll
-            for (int m = 0; m < NE; ++m) Sm[m] = sS[el][0][m][a];
+                for (int k = 0; k < NE; ++k) w[k] = 0.0f;
 #pragma unroll
-            for (int k = 0; k < NE; ++k) {
-                float s = 0.0f;
+                for (int c = 0; c < NE; ++c)
 #pragma unroll
-                for (int m = 0; m < NE; ++m) s += Sm[m] * sb[el][k][b][m];
-                sa[el][k][b][a] = __fdividef(s, h1 * (lxa + lyb + slz[el][k]) + h2);
+                    for (int k = 0; k < NE; ++k) w[k] += sS[el][2][c][k] * vv[c];
+#pragma unroll
+                for (int k = 0; k < NE; ++k) sa[el][k][b][a] = w[k];
             }
-        }
-        __syncthreads();
-        if (act) {
-            // back along a (thread (p = a, j = b))
-            float Sm[NE];
+            __syncthreads();
+            if (act) {
+                // modes along b (thread (a, j = b))
+                float Sm[NE];
 #pragma unroll
-            for (int m = 0; m < NE; ++m) Sm[m] = sS[el][0][a][m];
+                for (int m = 0; m < NE; ++m) Sm[m] = sS[el][1][m][b];
 #pragma unroll
-            for (int k = 0; k < NE; ++k) {
-                float s = 0.0f;
+                for (int k = 0; k < NE; ++k) {
+                    float sum = 0.0f;
 #pragma unroll
-                for (int m = 0; m < NE; ++m) s += Sm[m] * sa[el][k][b][m];
-                sb[el][k][b][a] = s;
+                    for (int m = 0; m < NE; ++m) sum += Sm[m] * sa[el][k][m][a];
+                    sb[el][k][b][a] = sum;
+                }
             }
-        }
-        __syncthreads();
-        if (act) {
-            // back along b (thread (p, q = b)), then along c in registers
-            float Sm[NE];
+            __syncthreads();
+            if (act) {
+                // modes along a (thread (i = a, j = b)), scaled by the inverse eigenvalue sum
+                float Sm[NE];
 #pragma unroll
-            for (int m = 0; m < NE; ++m) Sm[m] = sS[el][1][b][m];
+                for (int m = 0; m < NE; ++m) Sm[m] = sS[el][0][m][a];
 #pragma unroll
-            for (int k = 0; k < NE; ++k) {
-                float s = 0.0f;
+                for (int k = 0; k < NE; ++k) {
+                    float sum = 0.0f;
 #pragma unroll
-                for (int m = 0; m < NE; ++m) s += Sm[m] * sb[el][k][m][a];
-                w[k] = s;
+                    for (int m = 0; m < NE; ++m) sum += Sm[m] * sb[el][k][b][m];
+                    sa[el][k][b][a] = __fdividef(sum, h1 * (lxa + lyb + slz[el][k]) + h2);
+                }
             }
-            float *acce = acc + e * NP + (b - 1) * NQ + (a - 1);
-            float *Ue = EXT_OUT ? U + e * NEXT : nullptr;
-            auto line = [&](int c) {
-                float s = 0.0f;
+            __syncthreads();
+            if (act) {
+                // back along a (thread (p = a, j = b))
+                float Sm[NE];
 #pragma unroll
-                for (int k = 0; k < NE; ++k) s += sS[el][2][c][k] * w[k];
-                return s;
-            };
-            if (acol) {
-                if (EXT_OUT)
+                for (int m = 0; m < NE; ++m) Sm[m] = sS[el][0][a][m];
 #pragma unroll
-                    for (int c = 0; c < NE; ++c) Ue[ebase + c] = line(c);
-            } else {
+                for (int k = 0; k < NE; ++k) {
+                    float sum = 0.0f;
 #pragma unroll
-                for (int c = 1; c < NE - 1; ++c) acce[(c - 1) * NQ * NQ] = line(c);
-                if (EXT_OUT) {
-                    Ue[ebase] = line(0);
-                    Ue[ebase + 1] = line(NE - 1);
+                    for (int m = 0; m < NE; ++m) sum += Sm[m] * sa[el][k][b][m];
+                    sb[el][k][b][a] = sum;
+                }
+            }
+            __syncthreads();
+            if (act) {
+                // back along b (thread (p, q = b)), then along c in registers
+                float Sm[NE];
+#pragma unroll
+                for (int m = 0; m < NE; ++m) Sm[m] = sS[el][1][b][m];
+#pragma unroll
+                for (int k = 0; k < NE; ++k) {
+                    float sum = 0.0f;
+#pragma unroll
+                    for (int m = 0; m < NE; ++m) sum += Sm[m] * sb[el][k][m][a];
+                    w[k] = sum;
+                }
+                float *acce = acc + v * ld + e * NP + (b - 1) * NQ + (a - 1);
+                float *Ue = EXT_OUT ? U + v * E * NEXT + e * NEXT : nullptr;
+                auto line = [&](int c) {
+                    float sum = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < NE; ++k) sum += sS[el][2][c][k] * w[k];
+                    return sum;
+                };
+                if (acol) {
+                    if (EXT_OUT)
+#pragma unroll
+                        for (int c = 0; c < NE; ++c) Ue[ebase + c] = line(c);
+                } else {
+#pragma unroll
+                    for (int c = 1; c < NE - 1; ++c) acce[(c - 1) * NQ * NQ] = line(c);
+                    if (EXT_OUT) {
+                        Ue[ebase] = line(0);
+                        Ue[ebase + 1] = line(NE - 1);
+                    }
                 }
             }
         }
@@ -663,7 +675,7 @@ int launch_schwarz(const Level &L, bool ras, const float *r, const float *t, flo
 #define SEM_FDM(NE)                                                                         \
     case NE: {                                                                              \
         const int64_t groups = (L.E + FdmShape<NE>::EPB - 1) / FdmShape<NE>::EPB;           \
-        const dim3 grid((unsigned)std::min<int64_t>(groups, cap), (unsigned)vs.n);          \
+        const dim3 grid((unsigned)std::min<int64_t>(groups, cap));                          \
         if (ras)                                                                            \
             hipLaunchKernelGGL((fdm_kernel<NE, false>), grid, dim3(256), 0, s, L.E, L.sz_ix,  \
                                L.sz_S, L.sz_lam, r, t, L.nL, acc, U, (float)h1, (float)h2, vs); \
