@@ -214,9 +214,14 @@ inline int64_t balanced_grid(int64_t groups, int64_t cap)
 // is that of ax_kernel, in the same order.  PF: the next vector's u (or the
 // first vector of the next element) is loaded while the current one is
 // computed.  DTL: the rows of D^T come from an LDS table instead of
-// registers (fewer registers per lane, more waves per SIMD).
+// registers (fewer registers per lane, more waves per SIMD).  Without the
+// mass term the launch bound asks for two waves per SIMD: the FP64 form then
+// fits 248 VGPRs (some SGPRs kept in VGPR lanes) instead of 270 at one wave
+// per SIMD, and three fields at 16^3 take 48.5-49.5 instead of 51 us; with the
+// mass term the same bound spills 14 VGPRs and made the 32^3 lockstep p-MG
+// solve 1 ms slower, so that form keeps one wave per SIMD.
 template <int NQ, typename T, bool HELM, bool DOT, bool PF, bool DTL>
-__global__ void __launch_bounds__(AxShape<NQ>::THREADS)
+__global__ void __launch_bounds__(AxShape<NQ>::THREADS, HELM ? 1 : 2)
 ax_multi_kernel(int64_t E, const T *__restrict__ G, const T *__restrict__ B,
                 const T *__restrict__ Dg, T h1, T h2, const T *__restrict__ u, int64_t ldu,
                 T *__restrict__ w, int64_t ldw, VSet vs, double *__restrict__ partial, int64_t pst,
