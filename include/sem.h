@@ -252,6 +252,22 @@ SEM_API int sem_pcg_solve(sem_handle h, const double *b, double *x, const sem_so
                   sem_solve_stats *stats, void *stream);
 
 /*
+ * One application of the p-multigrid preconditioner of sem_pcg_solve (Sec. 3.4):
+ * z = M^{-1} r, the V-cycle the flexible CG applies to its residual, with the
+ * smoothing, transfers and coarse solve set by opts (h1, h2, smoother,
+ * cheb_degree, lanczos_steps, cheb_lo / cheb_hi, coarse_tol, coarse_maxit,
+ * use_graphs; precond is taken as SEM_PRECOND_PMG, k must be NULL).
+ *   r  device L-vector, FP64, replicated; its Dirichlet copies are ignored.
+ *   z  device L-vector, FP64, out: the V-cycle output (FP32 arithmetic inside
+ *      the smoothed levels), zero on Dirichlet copies.
+ * The preconditioner data (inverse diagonals, lambda_max estimates, Schwarz
+ * subdomains) are built on the first call for given coefficients and cached
+ * in the handle, as for sem_pcg_solve.  Needs a handle built with levels.
+ */
+SEM_API int sem_pmg_apply(sem_handle h, const double *r, double *z, const sem_solve_opts *opts,
+                          void *stream);
+
+/*
  * Allocation-free form of sem_pcg_solve, for callers that cannot allocate
  * device memory (code under HIP stream capture, tight serving loops,
  * harnesses that forbid hipMalloc): the same FP64 Jacobi-PCG, one right-hand

@@ -1680,33 +1680,12 @@ static int proj_update(sem_handle h, int v, const double *b, double *x, double h
 
 // nv solves with one operator, in lockstep: vector v's right-hand side and
 // iterate are b + v*ld and x + v*ld; every kernel serves the unconverged ones
-int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, const sem_solve_opts *o,
-              sem_solve_stats *st, hipStream_t s)
+// Preconditioner data for opts on the handle's levels (inverse diagonals,
+// the Chebyshev interval's lambda_max per smoothed level, the Schwarz data
+// when a Schwarz smoother is asked for), cached for constant coefficients.
+static int prepare_precond(sem_handle h, const sem_solve_opts *o, const SolveCfg &cfg, bool pmg, int nv,
+                           hipStream_t s)
 {
-    using clk = std::chrono::steady_clock;
-    const bool pmg = o->precond == SEM_PRECOND_PMG;
-    if (pmg && h->n_levels < 2) {
-        set_error("sem_pcg_solve: PMG needs a handle built with multigrid levels");
-        return SEM_EINVAL;
-    }
-    if (pmg && o->k) {
-        set_error("sem_pcg_solve: PMG supports constant coefficients only (k = NULL)");
-        return SEM_EINVAL;
-    }
-    const bool proj = o->proj_dim > 0;
-    if (proj && o->k) {
-        set_error("sem_pcg_solve: projected initial guesses need constant coefficients (k = NULL)");
-        return SEM_EINVAL;
-    }
-    SolveCfg cfg{o->h1, o->h2, o->tol, o->coarse_tol, o->maxit, std::max(1, o->check_every),
-                 std::max(1, o->cheb_degree), std::max(1, o->coarse_maxit),
-                 pmg ? o->smoother : SEM_SMOOTH_JACOBI};
-    const auto t0 = clk::now();
-    SEM_TRY(ensure_workspace(h, pmg, nv));
-    Workspace &w = h->ws;
-    const Level &F = h->lv[0];
-    const int64_t n = F.nL;
-    // preconditioner data, cached for constant coefficients
     PrecondKey key;
     key.valid = true;
     key.h1 = o->h1;
@@ -1745,6 +1724,36 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
     h->key.lo = key.lo;
     h->key.hi = key.hi;
     h->key.cheb_degree = key.cheb_degree;
+    return SEM_OK;
+}
+
+int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, const sem_solve_opts *o,
+              sem_solve_stats *st, hipStream_t s)
+{
+    using clk = std::chrono::steady_clock;
+    const bool pmg = o->precond == SEM_PRECOND_PMG;
+    if (pmg && h->n_levels < 2) {
+        set_error("sem_pcg_solve: PMG needs a handle built with multigrid levels");
+        return SEM_EINVAL;
+    }
+    if (pmg && o->k) {
+        set_error("sem_pcg_solve: PMG supports constant coefficients only (k = NULL)");
+        return SEM_EINVAL;
+    }
+    const bool proj = o->proj_dim > 0;
+    if (proj && o->k) {
+        set_error("sem_pcg_solve: projected initial guesses need constant coefficients (k = NULL)");
+        return SEM_EINVAL;
+    }
+    SolveCfg cfg{o->h1, o->h2, o->tol, o->coarse_tol, o->maxit, std::max(1, o->check_every),
+                 std::max(1, o->cheb_degree), std::max(1, o->coarse_maxit),
+                 pmg ? o->smoother : SEM_SMOOTH_JACOBI};
+    const auto t0 = clk::now();
+    SEM_TRY(ensure_workspace(h, pmg, nv));
+    Workspace &w = h->ws;
+    const Level &F = h->lv[0];
+    const int64_t n = F.nL;
+    SEM_TRY(prepare_precond(h, o, cfg, pmg, nv, s));
     SEM_HIP(hipStreamSynchronize(s));
     const auto t1 = clk::now();
 
@@ -1906,6 +1915,37 @@ int pcg_solve(sem_handle h, int nv, const double *b, double *x, int64_t ld, cons
         }
     }
     return rc;
+}
+
+// One application of the p-multigrid preconditioner, z = M^{-1} r: the
+// V-cycle the flexible CG applies to its residual, on an FP64 vector.
+int pmg_apply(sem_handle h, const double *r, double *z, const sem_solve_opts *o, hipStream_t s)
+{
+    if (h->n_levels < 2) {
+        set_error("sem_pmg_apply: the handle has no multigrid levels");
+        return SEM_EINVAL;
+    }
+    if (o->k) {
+        set_error("sem_pmg_apply: PMG supports constant coefficients only (k = NULL)");
+        return SEM_EINVAL;
+    }
+    sem_solve_opts oo = *o;
+    oo.precond = SEM_PRECOND_PMG;
+    SolveCfg cfg{oo.h1, oo.h2, oo.tol, oo.coarse_tol, oo.maxit, std::max(1, oo.check_every),
+                 std::max(1, oo.cheb_degree), std::max(1, oo.coarse_maxit), oo.smoother};
+    SEM_TRY(ensure_workspace(h, true, 1));
+    SEM_TRY(prepare_precond(h, &oo, cfg, true, 1, s));
+    Workspace &w = h->ws;
+    const Level &F = h->lv[0];
+    const int64_t n = F.nL;
+    const VSet one = VSet::one();
+    float *r32 = (float *)w.mg_r[0], *z32 = (float *)w.mg_x[0];  // V-cycle input, output
+    LAUNCH_B((convert_kernel<double, float>), n, one, s, n, one, n, r, n, r32);
+    LAUNCH_B((mask_kernel<float, float>), n, one, s, n, one, n, F.W32, r32);
+    SEM_TRY(vcycle_run(h, one, cfg, oo.use_graphs != 0, s));
+    LAUNCH_B((convert_kernel<float, double>), n, one, s, n, one, n, (const float *)z32, n, z);
+    LAUNCH_B((mask_kernel<double, float>), n, one, s, n, one, n, F.W32, z);
+    return SEM_OK;
 }
 
 // b = R QQ^T (B o f)
@@ -2228,6 +2268,16 @@ int sem_pcg_solve(sem_handle h, const double *b, double *x, const sem_solve_opts
     }
     SEM_TRY(check_solve_opts("sem_pcg_solve", o));
     return pcg_solve(h, 1, b, x, h->lv[0].nL, o, st, (hipStream_t)stream);
+}
+
+int sem_pmg_apply(sem_handle h, const double *r, double *z, const sem_solve_opts *o, void *stream)
+{
+    if (!h || !r || !z || !o) {
+        set_error("sem_pmg_apply: null argument");
+        return SEM_EINVAL;
+    }
+    SEM_TRY(check_solve_opts("sem_pmg_apply", o));
+    return pmg_apply(h, r, z, o, (hipStream_t)stream);
 }
 
 int sem_pcg_solve_multi(sem_handle h, int nrhs, const double *b, double *x, int64_t ld,

@@ -110,6 +110,7 @@ _SIGS = {
     "sem_advect": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP, ctypes.c_int64, _VP, ctypes.c_int64, _VP]),
     "sem_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(SemSolveOpts),
                                      ctypes.POINTER(SemSolveStats), _VP]),
+    "sem_pmg_apply": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(SemSolveOpts), _VP]),
     "sem_pcg_solve_noalloc": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(SemSolveOpts),
                                              ctypes.POINTER(SemSolveStats), _VP]),
     "sem_grad_k": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
@@ -459,6 +460,18 @@ class Sem:
         if raise_on_error and rc not in (SEM_OK, SEM_ENOCONV):
             _check(rc, "sem_pcg_solve")
         return x, st.as_dict(), rc
+
+    def pmg_apply(self, r, z=None, **kw):
+        """z = M^{-1} r, one application of the p-multigrid preconditioner
+        (sem_pmg_apply); keyword options as for solve()."""
+        torch = _torch()
+        o = self._opts(kw)
+        if z is None:
+            z = torch.empty_like(r)
+        _check(lib().sem_pmg_apply(self._handle(), _dev_ptr(r, torch.float64, self.n_local, "r"),
+                                   _dev_ptr(z, torch.float64, self.n_local, "z"), ctypes.byref(o),
+                                   _stream()), "sem_pmg_apply")
+        return z
 
     def solve_noalloc(self, b, x, raise_on_error=True, **kw):
         """sem_pcg_solve_noalloc: the Jacobi-PCG of solve() with every buffer

@@ -300,6 +300,53 @@ def test_pmg_fcg_reaches_1e8_and_matches_oracle():
     s.free()
 
 
+# SplitMix64 seed of the library's Lanczos / power-method start vectors
+LIBRARY_START_SEED = 0x5EED5EED
+
+
+@pytest.mark.parametrize("levels,bc,h2", [((7, 3, 1), "dirichlet", 10.0), ((5, 3, 2, 1), "dirichlet", 1.0),
+                                         ((9, 5, 1), "dirichlet", 4.0), ((7, 3, 1), "neumann", 2.0)])
+def test_pmg_apply_matches_oracle_vcycle(levels, bc, h2):
+    """One application of the p-multigrid preconditioner (sem_pmg_apply: FP32
+    Chebyshev-Jacobi smoothing, fused or unfused transfers, FP64 coarse
+    Jacobi-PCG) against the oracle's FP64 V-cycle with the same schedule,
+    interval, Lanczos start vector and coarse stopping rule: the mixed-
+    precision result's error against the FP64 oracle, per application.  It
+    is FP32 round-off of the smoothed levels (each FP32 operator application
+    within 1e-5 of FP64, more at N = 9) carried through the coarse-grid
+    correction, largest where the coarse problem is nearly singular (Neumann
+    boundaries, small h2): seen 1e-7 to 1.2e-4, the same with the default
+    coarse solve (1e-2, 20 iterations) and with one converged to 1e-12.
+    Bars: 5e-4 with the default coarse solve, 5e-5 (2e-4 at N = 9) with the
+    converged one; a dropped term, a wrong sign or a wrong index changes the
+    output at order one."""
+    print(f"[gpu] pmg apply {levels} {bc} h2={h2}", flush=True)
+    N, shape = levels[0], (3, 3, 2)
+    m = _mesh(shape, N, deform="cyclic", bc=bc)
+    mg = solvers.PMG(lambda n: _mesh(shape, n, bc=bc), m, levels=levels, h1=1.0, h2=h2,
+                     coarse_tol=1e-2, coarse_maxit=20)
+    mg.bounds = [(0.1 * lam, 1.1 * lam) for lam in
+                 (solvers.lanczos_lambda_max(lv, 20, seed=LIBRARY_START_SEED) for lv in mg.levels[:-1])]
+    lv = mg.levels[0]
+    rng = np.random.default_rng(7)
+    s = Sem(m, levels=levels)
+    rs = [lv.mask * oracle.qqt(m.gid, lv.B * inputs.gaussian_per_node(m.gid, 80)),
+          lv.mask * oracle.qqt(m.gid, rng.standard_normal(m.n_local) / oracle.multiplicity(m.gid))]
+    # the default coarse solve, then one converged to 1e-12 (the V-cycle is then
+    # a linear map, and only the FP32 round-off of the smoothed levels remains)
+    for ctol, cmax, bar in ((1e-2, 20, 5e-4), (1e-12, 5000, 2e-4 if N > 7 else 5e-5)):
+        mg.coarse_tol, mg.coarse_maxit = ctol, cmax
+        for k, r in enumerate(rs):
+            zo = mg.vcycle(r)
+            z = _host(s.pmg_apply(_dev(r), h1=1.0, h2=h2, coarse_tol=ctol, coarse_maxit=cmax))
+            rel = np.sqrt(np.sum(lv.W * (z - zo) ** 2) / np.sum(lv.W * zo ** 2))
+            print(f"[gpu] pmg apply {levels} {bc} coarse tol {ctol:g} rhs {k}: relative W-norm "
+                  f"difference {rel:.2e}", flush=True)
+            assert rel <= bar, (ctol, k, rel)
+            assert np.all(z[lv.mask == 0] == 0.0)
+    s.free()
+
+
 @pytest.fixture
 def poisoned_workspace(monkeypatch):
     """New solver workspace filled with 0xFF bytes (NaN as FP32 and FP64)."""
