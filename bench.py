@@ -301,7 +301,22 @@ def bench_pcg(args, torch, sem_mod, inputs):
         gbs = bpp * s.n_local / (ms_a * 1e-3) / 1e9
         ooc[label] = {"ms": round(ms_a, 4), "algorithmic_bytes": bpp * s.n_local,
                       "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    del wv
+    # dL/dk (sem_grad_k, the adjoint's coefficient gradient) on the same mesh:
+    # u, lam and six G read, gk written, 72 B per local point
+    lam = torch.flip(b0, (0,))
+    for _ in range(3):
+        s.grad_k(b0, lam, h1=1.0, out=wv)
+    ev0.record(stream)
+    for _ in range(10):
+        s.grad_k(b0, lam, h1=1.0, out=wv)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_gk = ev0.elapsed_time(ev1) / 10
+    gbs = 72 * s.n_local / (ms_gk * 1e-3) / 1e9
+    gk_rec = {"call": "sem_grad_k on the 32^3 mesh (dL/dk = -h1 (D lam)^T G (D u) per copy)",
+              "ms": round(ms_gk, 4), "algorithmic_bytes": 72 * s.n_local,
+              "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del wv, lam
     # every solution's true residual recomputed by the CPU oracle
     oracle_res = {}
     if not args.no_cpu:
@@ -340,6 +355,7 @@ def bench_pcg(args, torch, sem_mod, inputs):
             out[pre]["oracle_true_rel_res"] = oracle_res[pre]
         out[pre]["phases_ms_rhs0"] = phases[pre]
     out["ax_out_of_cache"] = ooc
+    out["grad_k"] = gk_rec
     for pre, v in lock.items():
         out[pre + "_lockstep"] = v
         v["speedup_vs_independent"] = round(out[pre]["ms_total"] / v["ms_total"], 3)

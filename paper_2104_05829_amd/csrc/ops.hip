@@ -275,9 +275,85 @@ __global__ void grad_k_kernel(int64_t nL, int nq, const double *__restrict__ G,
     gk[q] = -h1 * s;
 }
 
+// The same pointwise product for elements that fit one wavefront (nq <= 8),
+// in the element operator's layout: thread (i, j) holds the k-lines of u and
+// lam in registers (t-derivatives there, D entries wave-uniform), the r- and
+// s-derivatives read LDS rows; every element's u, lam, G and gk move once
+// (72 B per point), coalesced.  The sums run in the same order as above.
+template <int NQ>
+__global__ void __launch_bounds__(64)
+grad_k_elem_kernel(int64_t E, const double *__restrict__ G, const double *__restrict__ D,
+                   const double *__restrict__ u, const double *__restrict__ lam, double h1,
+                   double *__restrict__ gk)
+{
+    constexpr int TPE = NQ * NQ, EPB = 64 / TPE, NP = NQ * NQ * NQ, LD = (NQ % 2 == 0) ? NQ + 1 : NQ;
+    __shared__ double su[EPB][NQ][NQ][LD];
+    __shared__ double sl[EPB][NQ][NQ][LD];
+    const int tid = threadIdx.x;
+    const int el = tid / TPE, ij = tid - el * TPE;
+    const int i = ij % NQ, j = ij / NQ;
+    const int64_t e = (int64_t)blockIdx.x * EPB + el;
+    const bool act = el < EPB && e < E;
+    double ru[NQ], rl[NQ], Di[NQ], Dj[NQ];
+#pragma unroll
+    for (int l = 0; l < NQ; ++l) {
+        Di[l] = D[i * NQ + l];
+        Dj[l] = D[j * NQ + l];
+    }
+    const int64_t base = (act ? e : 0) * NP + ij;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        ru[k] = act ? u[base + k * TPE] : 0.0;
+        rl[k] = act ? lam[base + k * TPE] : 0.0;
+        if (el < EPB) {
+            su[el][k][j][i] = ru[k];
+            sl[el][k][j][i] = rl[k];
+        }
+    }
+    // one wavefront: order the LDS writes before the reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (!act) return;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        double a0 = 0, a1 = 0, a2 = 0, c0 = 0, c1 = 0, c2 = 0;
+#pragma unroll
+        for (int l = 0; l < NQ; ++l) {
+            const double dk = D[k * NQ + l];
+            a0 += Di[l] * sl[el][k][j][l];
+            a1 += Dj[l] * sl[el][k][l][i];
+            a2 += dk * rl[l];
+            c0 += Di[l] * su[el][k][j][l];
+            c1 += Dj[l] * su[el][k][l][i];
+            c2 += dk * ru[l];
+        }
+        const double2 *g2 = reinterpret_cast<const double2 *>(G + (base + k * TPE) * 6);
+        const double2 ga = g2[0], gb = g2[1], gc = g2[2];
+        const double g11 = ga.x, g12 = ga.y, g13 = gb.x, g22 = gb.y, g23 = gc.x, g33 = gc.y;
+        const double sum = a0 * (g11 * c0 + g12 * c1 + g13 * c2) + a1 * (g12 * c0 + g22 * c1 + g23 * c2)
+                         + a2 * (g13 * c0 + g23 * c1 + g33 * c2);
+        gk[base + k * TPE] = -h1 * sum;
+    }
+}
+
 int launch_grad_k(const Level &L, const double *u, const double *lam, double h1, double *gk,
                   hipStream_t s)
 {
+#define SEM_GK(NQ)                                                                          \
+    case NQ: {                                                                              \
+        constexpr int EPB = 64 / (NQ * NQ);                                                 \
+        const int64_t nb = (L.E + EPB - 1) / EPB;                                           \
+        hipLaunchKernelGGL(grad_k_elem_kernel<NQ>, dim3((unsigned)nb), dim3(64), 0, s, L.E, L.G, \
+                           L.D, u, lam, h1, gk);                                            \
+        SEM_HIP(hipGetLastError());                                                         \
+        return SEM_OK;                                                                      \
+    }
+    switch (L.nq) {
+        SEM_GK(2) SEM_GK(3) SEM_GK(4) SEM_GK(5) SEM_GK(6) SEM_GK(7) SEM_GK(8)
+    default: break;
+    }
+#undef SEM_GK
     const int bs = 256;
     const int64_t nb = (L.nL + bs - 1) / bs;
     hipLaunchKernelGGL(grad_k_kernel, dim3((unsigned)nb), dim3(bs), 0, s, L.nL, L.nq, L.G, L.D, u,

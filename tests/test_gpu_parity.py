@@ -392,10 +392,13 @@ def test_solves_never_read_unwritten_workspace(smoother, poisoned_workspace):
     s.free()
 
 
-def test_grad_k_parity():
-    print("[gpu] grad_k", flush=True)
-    N = 7
-    m = _mesh((2, 3, 2), N, deform="cyclic")
+@pytest.mark.parametrize("shape,N", [((2, 3, 2), 7), ((3, 2, 3), 3), ((4, 3, 2), 1), ((2, 2, 1), 9),
+                                     ((5, 4, 3), 7)])
+def test_grad_k_parity(shape, N):
+    """dL/dk = -h1 (D lam)^T G (D u) per copy against the oracle within 1e-12
+    (element-layout kernel for N <= 7, one thread per point above)."""
+    print(f"[gpu] grad_k {shape} N={N}", flush=True)
+    m = _mesh(shape, N, deform="cyclic")
     u = inputs.gaussian_per_node(m.gid, 1)
     lam = inputs.gaussian_per_node(m.gid, 2)
     s = Sem(m)
