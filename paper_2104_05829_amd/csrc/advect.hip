@@ -44,7 +44,7 @@ struct AdvShape {
 // sQ [k][j][a] = Jd u (contraction over i)
 template <int NQ, int M>
 __device__ __forceinline__ void stage_rows(const double *__restrict__ J, const double *__restrict__ Jd,
-                                           const double *sU, double *sP, double *sQ, bool need_q)
+                                           const double *sU, double *sP, double *sQ)
 {
     const int t = threadIdx.x;
     if (t < NQ * NQ) {
@@ -58,10 +58,10 @@ __device__ __forceinline__ void stage_rows(const double *__restrict__ J, const d
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
                 p += J[a * NQ + i] * r[i];
-                if (need_q) q += Jd[a * NQ + i] * r[i];
+                q += Jd[a * NQ + i] * r[i];
             }
             sP[(k * NQ + j) * M + a] = p;
-            if (need_q) sQ[(k * NQ + j) * M + a] = q;
+            sQ[(k * NQ + j) * M + a] = q;
         }
     }
 }
@@ -372,12 +372,11 @@ __global__ void __launch_bounds__((Adv3Shape<NQ, M>::THREADS))
     }
 }
 
-// Values (GRAD = false: out[e * ostride + p]) or reference gradients (GRAD:
-// out[e * ostride + q * M^3 + p], q = r, s, t) of the interpolant of the
-// L-vector u at the Gauss points p = a + M b + M^2 c.
-template <int NQ, int M, bool GRAD>
+// Reference gradients out[e * ostride + q * M^3 + p], q = r, s, t, of the
+// interpolant of the L-vector u at the Gauss points p = a + M b + M^2 c.
+template <int NQ, int M>
 __global__ void __launch_bounds__(256)
-    fine_eval_kernel(int64_t E, const double *__restrict__ J, const double *__restrict__ Jd,
+    fine_grad_kernel(int64_t E, const double *__restrict__ J, const double *__restrict__ Jd,
                      const double *__restrict__ u, double *__restrict__ out, int64_t ostride)
 {
     using S = AdvShape<NQ, M>;
@@ -398,42 +397,24 @@ __global__ void __launch_bounds__(256)
         const double *ue = u + e * S::NP;
         for (int i = t; i < S::NP; i += blockDim.x) sU[i] = ue[i];
         __syncthreads();
-        stage_rows<NQ, M>(J, Jd, sU, sP, sQ, GRAD);
+        stage_rows<NQ, M>(J, Jd, sU, sP, sQ);
         __syncthreads();
         if (col) {
             double *oe = out + e * ostride + t;
-            if (GRAD) {
-                double Tr[NQ], Ts[NQ], Tt[NQ];
-                stage_cols<NQ, M>(Jb, Jdb, a, sP, sQ, Tr, Ts, Tt);
+            double Tr[NQ], Ts[NQ], Tt[NQ];
+            stage_cols<NQ, M>(Jb, Jdb, a, sP, sQ, Tr, Ts, Tt);
 #pragma unroll
-                for (int c = 0; c < M; ++c) {
-                    double dr = 0.0, ds = 0.0, dt = 0.0;
-#pragma unroll
-                    for (int k = 0; k < NQ; ++k) {
-                        dr += J[c * NQ + k] * Tr[k];
-                        ds += J[c * NQ + k] * Ts[k];
-                        dt += Jd[c * NQ + k] * Tt[k];
-                    }
-                    oe[c * S::MM] = dr;
-                    oe[S::M3 + c * S::MM] = ds;
-                    oe[2 * S::M3 + c * S::MM] = dt;
-                }
-            } else {
-                double Tt[NQ];
+            for (int c = 0; c < M; ++c) {
+                double dr = 0.0, ds = 0.0, dt = 0.0;
 #pragma unroll
                 for (int k = 0; k < NQ; ++k) {
-                    double x = 0.0;
-#pragma unroll
-                    for (int j = 0; j < NQ; ++j) x += Jb[j] * sP[(k * NQ + j) * M + a];
-                    Tt[k] = x;
+                    dr += J[c * NQ + k] * Tr[k];
+                    ds += J[c * NQ + k] * Ts[k];
+                    dt += Jd[c * NQ + k] * Tt[k];
                 }
-#pragma unroll
-                for (int c = 0; c < M; ++c) {
-                    double v = 0.0;
-#pragma unroll
-                    for (int k = 0; k < NQ; ++k) v += J[c * NQ + k] * Tt[k];
-                    oe[c * S::MM] = v;
-                }
+                oe[c * S::MM] = dr;
+                oe[S::M3 + c * S::MM] = ds;
+                oe[2 * S::M3 + c * S::MM] = dt;
             }
         }
         __syncthreads();  // sU / sP are rewritten for the next element
@@ -475,23 +456,81 @@ __global__ void metric_kernel(int64_t E, int M, const double *__restrict__ wq, d
     }
 }
 
-// ct[e][q][p] = sum_d F[e][3 q + d][p] ct[e][d][p] (in place: interpolated
-// velocity components on entry)
-__global__ void contra_kernel(int64_t E, int64_t M3, const double *__restrict__ F, double *__restrict__ ct)
+// ct[e][q][p] = sum_d F[e][3 q + d][p] (J3 c_d)[p]: the three velocity
+// components interpolated to the Gauss points and turned contravariant in one
+// pass.  Lane t = a + M b owns the Gauss column (b, a) as in the advection
+// kernel; the components go through LDS one after another (contraction over
+// i on GLL rows, then over j and k on the column in registers), the lane
+// keeps its 3 M interpolated values in registers, and the column's nine
+// factors are read and the three products written point by point, so the
+// interpolated velocity never reaches memory.
+template <int NQ, int M>
+__global__ void __launch_bounds__((AdvShape<NQ, M>::THREADS))
+    velocity_kernel(int64_t E, const double *__restrict__ J, const double *__restrict__ F,
+                    const double *__restrict__ c, int64_t ldc, double *__restrict__ ct)
 {
-    const int64_t n = E * M3;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = g / M3, p = g % M3;
-        const double *Fe = F + e * 9 * M3 + p;
-        double *ce = ct + e * 3 * M3 + p;
-        const double v0 = ce[0], v1 = ce[M3], v2 = ce[2 * M3];
-        double o[3];
+    using S = AdvShape<NQ, M>;
+    constexpr int NP = S::NP, MM = S::MM, M3 = S::M3, TH = S::THREADS;
+    __shared__ double sU[NP];
+    __shared__ double sP[NQ * NQ * M];
+    const int t = threadIdx.x;
+    const bool col = t < MM;
+    const int a = col ? t % M : 0, b = col ? t / M : 0;
+    double Jb[NQ];
 #pragma unroll
-        for (int q = 0; q < 3; ++q)
-            o[q] = Fe[(3 * q) * M3] * v0 + Fe[(3 * q + 1) * M3] * v1 + Fe[(3 * q + 2) * M3] * v2;
+    for (int j = 0; j < NQ; ++j) Jb[j] = J[b * NQ + j];
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        double v[3][M];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) ce[q * M3] = o[q];
+        for (int d = 0; d < 3; ++d) {
+            const double *ue = c + d * ldc + e * NP;
+            for (int i = t; i < NP; i += TH) sU[i] = ue[i];
+            __syncthreads();
+            // over i on GLL rows (k, j): sP[k][j][a] = (J u)[k][j][a]
+            for (int r = t; r < NQ * NQ; r += TH) {
+                double ri[NQ];
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) ri[i] = sU[r * NQ + i];
+#pragma unroll
+                for (int a2 = 0; a2 < M; ++a2) {
+                    double p = 0.0;
+#pragma unroll
+                    for (int i = 0; i < NQ; ++i) p += J[a2 * NQ + i] * ri[i];
+                    sP[r * M + a2] = p;
+                }
+            }
+            __syncthreads();
+            if (col) {
+                double Tt[NQ];
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) {
+                    double x = 0.0;
+#pragma unroll
+                    for (int j = 0; j < NQ; ++j) x += Jb[j] * sP[(k * NQ + j) * M + a];
+                    Tt[k] = x;
+                }
+#pragma unroll
+                for (int cc = 0; cc < M; ++cc) {
+                    double x = 0.0;
+#pragma unroll
+                    for (int k = 0; k < NQ; ++k) x += J[cc * NQ + k] * Tt[k];
+                    v[d][cc] = x;
+                }
+            }
+            __syncthreads();  // sU and sP are rewritten for the next component
+        }
+        if (col) {
+            const double *Fe = F + e * 9 * M3 + t;
+            double *ce = ct + e * 3 * M3 + t;
+#pragma unroll
+            for (int cc = 0; cc < M; ++cc) {
+                const int p = cc * MM;
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    ce[q * M3 + p] = Fe[(3 * q) * M3 + p] * v[0][cc] + Fe[(3 * q + 1) * M3 + p] * v[1][cc] +
+                                     Fe[(3 * q + 2) * M3 + p] * v[2][cc];
+            }
+        }
     }
 }
 
@@ -515,24 +554,37 @@ int64_t adv_grid(const Level &L)
 #define SEM_ADV_PAIRS(X) \
     X(2, 2) X(2, 3) X(3, 4) X(3, 5) X(4, 5) X(4, 6) X(5, 7) X(5, 8) X(6, 8) X(6, 9) X(7, 10) X(7, 11) X(8, 11) X(8, 12)
 
-int launch_fine_eval(const Level &L, int M, bool grad, const double *J, const double *Jd, const double *u,
-                     double *out, int64_t ostride, hipStream_t s)
+int launch_fine_grad(const Level &L, int M, const double *J, const double *Jd, const double *u, double *out,
+                     int64_t ostride, hipStream_t s)
 {
     const dim3 grid((unsigned)adv_grid(L));
-#define SEM_FE(NQ_, M_)                                                                              \
+#define SEM_FG(NQ_, M_)                                                                              \
     if (L.nq == NQ_ && M == M_) {                                                                    \
-        const dim3 block(AdvShape<NQ_, M_>::THREADS);                                                \
-        if (grad)                                                                                    \
-            hipLaunchKernelGGL((fine_eval_kernel<NQ_, M_, true>), grid, block, 0, s, L.E, J, Jd, u, out, \
-                               ostride);                                                             \
-        else                                                                                         \
-            hipLaunchKernelGGL((fine_eval_kernel<NQ_, M_, false>), grid, block, 0, s, L.E, J, Jd, u,     \
-                               out, ostride);                                                        \
+        hipLaunchKernelGGL((fine_grad_kernel<NQ_, M_>), grid, dim3(AdvShape<NQ_, M_>::THREADS), 0, s, L.E, J, \
+                           Jd, u, out, ostride);                                                     \
         SEM_HIP(hipGetLastError());                                                                  \
         return SEM_OK;                                                                               \
     }
-    SEM_ADV_PAIRS(SEM_FE)
-#undef SEM_FE
+    SEM_ADV_PAIRS(SEM_FG)
+#undef SEM_FG
+    set_error("advection: no kernel for N = %d, M = %d", L.N, M);
+    return SEM_EINVAL;
+}
+
+int launch_velocity(const Level &L, int M, const double *J, const double *F, const double *c, int64_t ldc,
+                    double *ct, hipStream_t s)
+{
+    const int64_t cap = (int64_t)(L.n_cu > 0 ? L.n_cu : 256) * 16;
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(L.E, cap)));
+#define SEM_VEL(NQ_, M_)                                                                            \
+    if (L.nq == NQ_ && M == M_) {                                                                   \
+        hipLaunchKernelGGL((velocity_kernel<NQ_, M_>), grid, dim3(AdvShape<NQ_, M_>::THREADS), 0, s, \
+                           L.E, J, F, c, ldc, ct);                                                  \
+        SEM_HIP(hipGetLastError());                                                                 \
+        return SEM_OK;                                                                              \
+    }
+    SEM_ADV_PAIRS(SEM_VEL)
+#undef SEM_VEL
     set_error("advection: no kernel for N = %d, M = %d", L.N, M);
     return SEM_EINVAL;
 }
@@ -612,7 +664,7 @@ int advect_setup(sem_handle h, int M, hipStream_t s)
     SEM_HIP(hipMalloc(&A.F, sizeof(double) * 9 * M3 * L.E));
     const double *X[3] = {h->cx, h->cy, h->cz};
     for (int d = 0; d < 3; ++d)
-        SEM_TRY(launch_fine_eval(L, M, true, A.J, A.Jd, X[d], A.F + 3 * d * M3, 9 * M3, s));
+        SEM_TRY(launch_fine_grad(L, M, A.J, A.Jd, X[d], A.F + 3 * d * M3, 9 * M3, s));
     int *bad = nullptr;
     SEM_HIP(hipMalloc(&bad, sizeof(int)));
     int hbad = 0;
@@ -712,14 +764,7 @@ int sem_advect_velocity(sem_handle h, const double *c, int64_t ldc, double *ct, 
         return SEM_EINVAL;
     }
     const hipStream_t s = (hipStream_t)stream;
-    const int64_t M3 = (int64_t)A.M * A.M * A.M;
-    for (int d = 0; d < 3; ++d)
-        SEM_TRY(launch_fine_eval(L, A.M, false, A.J, A.Jd, c + d * ldc, ct + d * M3, 3 * M3, s));
-    const int64_t n = L.E * M3;
-    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
-    hipLaunchKernelGGL(contra_kernel, dim3(blocks), dim3(256), 0, s, L.E, M3, (const double *)A.F, ct);
-    SEM_HIP(hipGetLastError());
-    return SEM_OK;
+    return launch_velocity(L, A.M, A.J, A.F, c, ldc, ct, s);
 }
 
 int sem_advect(sem_handle h, const double *ct, int nf, const double *w, int64_t ldw, double *out, int64_t ldo,
