@@ -455,37 +455,44 @@ int build_schwarz(Level &L, hipStream_t s)
 }
 
 // ------------------------------------------------------------------ kernels
-// Local FDM solves, EPB elements per 256-thread workgroup: thread (a, b) of an
-// element's ne x ne point columns keeps the c-line in registers; the
-// element's S matrices and eigenvalues along c sit in LDS; the b and a
-// contractions run through two LDS buffers.  Own points are read directly and
-// written to acc; extension points are gathered through the compact map and
-// (ASM) written to U.  The eigenbases and the extension map of an element are
-// loaded once and serve every vector of the batch in turn.  FP32.
+// Local FDM solves, EPB elements per workgroup, ne^2 threads per element.
+// Every 1D transform is applied by threads that each own one whole line of
+// the direction transformed: the c-lines by thread (a, b) in registers
+// (gathered inputs, and the final transform back), the b-lines by thread
+// (a, k) and the a-lines by thread (b, k), read from and written to two LDS
+// buffers, so a thread reads ne values per transform rather than ne^2, and the
+// forward a transform, the division by the eigenvalue sum and the transform
+// back along a run in one pass on the thread's row.  The rows of the
+// element's S matrices are read from LDS (every lane of the element reads the
+// same row).  Own points are read directly and written to acc; extension
+// points are gathered through the compact map and (ASM) written to U.  The
+// eigenbases and the extension map of an element are loaded once and serve
+// every vector of the batch in turn.  FP32.
 template <int NE>
 struct FdmShape {
     static constexpr int NQ = NE - 2, NE2 = NE * NE, THREADS = 256;
     static constexpr int EPB = THREADS / NE2;
     static constexpr int NEXT = NE * NE * NE - NQ * NQ * NQ;
     static constexpr int LDP = NE + 1;
+    static constexpr int NEP = (NE + 3) & ~3;  // S rows padded to 16 bytes
 };
 
 template <int NE, bool EXT_OUT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(FdmShape<NE>::THREADS)
 fdm_kernel(int64_t E, const int32_t *__restrict__ ix, const float *__restrict__ Sg,
            const float *__restrict__ lamg, const float *__restrict__ r, const float *__restrict__ t,
            int64_t ld, float *__restrict__ acc, float *__restrict__ U, float h1, float h2, VSet vs)
 {
     using F = FdmShape<NE>;
-    constexpr int NQ = F::NQ, NE2 = F::NE2, EPB = F::EPB, NEXT = F::NEXT, LDP = F::LDP;
+    constexpr int NQ = F::NQ, NE2 = F::NE2, EPB = F::EPB, NEXT = F::NEXT, LDP = F::LDP, NEP = F::NEP;
     constexpr int NP = NQ * NQ * NQ;
-    __shared__ float sS[EPB][3][NE][NE];  // Sx, Sy, Sz of each element
-    __shared__ float slz[EPB][NE];
-    __shared__ float sa[EPB][NE][NE][LDP];  // [c][b][a]
+    __shared__ __align__(16) float sS[EPB][3][NE][NEP];  // Sx, Sy, Sz of each element, rows [m][.]
+    __shared__ float sl[EPB][3][NE];                     // eigenvalues along x, y, z
+    __shared__ float sa[EPB][NE][NE][LDP];               // [c][b][a]
     __shared__ float sb[EPB][NE][NE][LDP];
     const int tid = threadIdx.x;
     const int el = tid / NE2, ij = tid - el * NE2;
-    const int a = ij % NE, b = ij / NE;
+    const int a = ij % NE, b = ij / NE;  // also (x, k) of the line-owner stages
     const bool lane = el < EPB;
     const bool acol = a == 0 || a == NE - 1 || b == 0 || b == NE - 1;  // border column
     // extension slots of this column: ebase + c (border column), or ebase and
@@ -499,14 +506,11 @@ fdm_kernel(int64_t E, const int32_t *__restrict__ ix, const float *__restrict__ 
         // the element's eigenbases and eigenvalues and this column's
         // extension copies, once for every vector of the batch
         int32_t q[NE];
-        float lxa = 1.0f, lyb = 1.0f;
         if (act) {
             const float *Se = Sg + e * 3 * NE2;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) (&sS[el][d][0][0])[ij] = Se[d * NE2 + ij];
-            if (ij < NE) slz[el][ij] = lamg[e * 3 * NE + 2 * NE + ij];
-            lxa = lamg[e * 3 * NE + a];
-            lyb = lamg[e * 3 * NE + NE + b];
+            for (int d = 0; d < 3; ++d) sS[el][d][b][a] = Se[d * NE2 + ij];
+            if (ij < 3 * NE) (&sl[el][0][0])[ij] = lamg[e * 3 * NE + ij];
             const int32_t *ixe = ix + e * NEXT;
             if (acol) {
 #pragma unroll
@@ -516,11 +520,12 @@ fdm_kernel(int64_t E, const int32_t *__restrict__ ix, const float *__restrict__ 
                 q[NE - 1] = ixe[ebase + 1];
             }
         }
+        __syncthreads();  // sS, sl ready
         for (int f = 0; f < vs.n; ++f) {
             const int64_t v = vs.at(f);
             const float *rv = r + v * ld;
             const float *tv = t ? t + v * ld : nullptr;
-            float vv[NE], w[NE];
+            float vv[NE];
             if (act) {
                 auto gather = [&](int32_t qq) {
                     return qq >= 0 ? (tv ? rv[qq] - tv[qq] : rv[qq]) : 0.0f;
@@ -537,80 +542,97 @@ fdm_kernel(int64_t E, const int32_t *__restrict__ ix, const float *__restrict__ 
                         vv[c] = te ? re[(c - 1) * NQ * NQ] - te[(c - 1) * NQ * NQ] : re[(c - 1) * NQ * NQ];
                     vv[NE - 1] = gather(q[NE - 1]);
                 }
-            }
-            __syncthreads();  // sS, slz ready; the previous vector's LDS consumed
-            if (act) {
-                // modes along c (rows of Sz read contiguously)
+                // modes along c: w[k] = sum_c Sz[c][k] vv[c]
+                float w[NE];
 #pragma unroll
                 for (int k = 0; k < NE; ++k) w[k] = 0.0f;
 #pragma unroll
-                for (int c = 0; c < NE; ++c)
+                for (int c = 0; c < NE; ++c) {
+                    const float *Sr = &sS[el][2][c][0];
 #pragma unroll
-                    for (int k = 0; k < NE; ++k) w[k] += sS[el][2][c][k] * vv[c];
+                    for (int k = 0; k < NE; ++k) w[k] += Sr[k] * vv[c];
+                }
 #pragma unroll
                 for (int k = 0; k < NE; ++k) sa[el][k][b][a] = w[k];
             }
             __syncthreads();
             if (act) {
-                // modes along b (thread (a, j = b))
-                float Sm[NE];
+                // modes along b on the line (a, k = b): y[j] = sum_m Sy[m][j] x[m]
+                const int k = b;
+                float x[NE], y[NE];
 #pragma unroll
-                for (int m = 0; m < NE; ++m) Sm[m] = sS[el][1][m][b];
+                for (int m = 0; m < NE; ++m) x[m] = sa[el][k][m][a];
 #pragma unroll
-                for (int k = 0; k < NE; ++k) {
+                for (int j = 0; j < NE; ++j) y[j] = 0.0f;
+#pragma unroll
+                for (int m = 0; m < NE; ++m) {
+                    const float *Sr = &sS[el][1][m][0];
+#pragma unroll
+                    for (int j = 0; j < NE; ++j) y[j] += Sr[j] * x[m];
+                }
+#pragma unroll
+                for (int j = 0; j < NE; ++j) sb[el][k][j][a] = y[j];
+            }
+            __syncthreads();
+            if (act) {
+                // the row (b = a, k = b) along a: modes, division by the
+                // eigenvalue sum, and back
+                const int bb = a, k = b;
+                float x[NE], y[NE];
+#pragma unroll
+                for (int m = 0; m < NE; ++m) x[m] = sb[el][k][bb][m];
+#pragma unroll
+                for (int i = 0; i < NE; ++i) y[i] = 0.0f;
+#pragma unroll
+                for (int m = 0; m < NE; ++m) {
+                    const float *Sr = &sS[el][0][m][0];
+#pragma unroll
+                    for (int i = 0; i < NE; ++i) y[i] += Sr[i] * x[m];
+                }
+                const float lyz = sl[el][1][bb], lzk = sl[el][2][k];
+#pragma unroll
+                for (int i = 0; i < NE; ++i) y[i] *= __builtin_amdgcn_rcpf(h1 * (sl[el][0][i] + lyz + lzk) + h2);
+                // the rows of Sx are read again below rather than kept in
+                // registers from the forward pass (that would cost ne^2 VGPRs)
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int i = 0; i < NE; ++i) {
+                    const float *Sr = &sS[el][0][i][0];
                     float sum = 0.0f;
 #pragma unroll
-                    for (int m = 0; m < NE; ++m) sum += Sm[m] * sa[el][k][m][a];
-                    sb[el][k][b][a] = sum;
+                    for (int m = 0; m < NE; ++m) sum += Sr[m] * y[m];
+                    sa[el][k][bb][i] = sum;
                 }
             }
             __syncthreads();
             if (act) {
-                // modes along a (thread (i = a, j = b)), scaled by the inverse eigenvalue sum
-                float Sm[NE];
+                // back along b on the line (a, k = b)
+                const int k = b;
+                float x[NE];
 #pragma unroll
-                for (int m = 0; m < NE; ++m) Sm[m] = sS[el][0][m][a];
+                for (int m = 0; m < NE; ++m) x[m] = sa[el][k][m][a];
 #pragma unroll
-                for (int k = 0; k < NE; ++k) {
+                for (int j = 0; j < NE; ++j) {
+                    const float *Sr = &sS[el][1][j][0];
                     float sum = 0.0f;
 #pragma unroll
-                    for (int m = 0; m < NE; ++m) sum += Sm[m] * sb[el][k][b][m];
-                    sa[el][k][b][a] = __fdividef(sum, h1 * (lxa + lyb + slz[el][k]) + h2);
+                    for (int m = 0; m < NE; ++m) sum += Sr[m] * x[m];
+                    sb[el][k][j][a] = sum;
                 }
             }
             __syncthreads();
             if (act) {
-                // back along a (thread (p = a, j = b))
-                float Sm[NE];
+                // back along c on the column (a, b), in registers
+                float w[NE];
 #pragma unroll
-                for (int m = 0; m < NE; ++m) Sm[m] = sS[el][0][a][m];
-#pragma unroll
-                for (int k = 0; k < NE; ++k) {
-                    float sum = 0.0f;
-#pragma unroll
-                    for (int m = 0; m < NE; ++m) sum += Sm[m] * sa[el][k][b][m];
-                    sb[el][k][b][a] = sum;
-                }
-            }
-            __syncthreads();
-            if (act) {
-                // back along b (thread (p, q = b)), then along c in registers
-                float Sm[NE];
-#pragma unroll
-                for (int m = 0; m < NE; ++m) Sm[m] = sS[el][1][b][m];
-#pragma unroll
-                for (int k = 0; k < NE; ++k) {
-                    float sum = 0.0f;
-#pragma unroll
-                    for (int m = 0; m < NE; ++m) sum += Sm[m] * sb[el][k][m][a];
-                    w[k] = sum;
-                }
+                for (int k = 0; k < NE; ++k) w[k] = sb[el][k][b][a];
                 float *acce = acc + v * ld + e * NP + (b - 1) * NQ + (a - 1);
                 float *Ue = EXT_OUT ? U + v * E * NEXT + e * NEXT : nullptr;
                 auto line = [&](int c) {
+                    const float *Sr = &sS[el][2][c][0];
                     float sum = 0.0f;
 #pragma unroll
-                    for (int k = 0; k < NE; ++k) sum += sS[el][2][c][k] * w[k];
+                    for (int k = 0; k < NE; ++k) sum += Sr[k] * w[k];
                     return sum;
                 };
                 if (acol) {
@@ -626,6 +648,9 @@ fdm_kernel(int64_t E, const int32_t *__restrict__ ix, const float *__restrict__ 
                     }
                 }
             }
+            // the next vector's first LDS writes (sa) follow this vector's
+            // last sa reads (before the barrier above); its sb writes follow
+            // a barrier every thread reaches after the reads of sb here
         }
     }
 }
@@ -671,19 +696,20 @@ int launch_schwarz(const Level &L, bool ras, const float *r, const float *t, flo
         set_error("Schwarz smoother not built on this level");
         return SEM_EINVAL;
     }
-    const int64_t cap = (int64_t)(L.n_cu > 0 ? L.n_cu : 256) * 8;
-#define SEM_FDM(NE)                                                                         \
-    case NE: {                                                                              \
-        const int64_t groups = (L.E + FdmShape<NE>::EPB - 1) / FdmShape<NE>::EPB;           \
-        const dim3 grid((unsigned)std::min<int64_t>(groups, cap));                          \
-        if (ras)                                                                            \
-            hipLaunchKernelGGL((fdm_kernel<NE, false>), grid, dim3(256), 0, s, L.E, L.sz_ix,  \
-                               L.sz_S, L.sz_lam, r, t, L.nL, acc, U, (float)h1, (float)h2, vs); \
-        else                                                                                \
-            hipLaunchKernelGGL((fdm_kernel<NE, true>), grid, dim3(256), 0, s, L.E, L.sz_ix,   \
-                               L.sz_S, L.sz_lam, r, t, L.nL, acc, U, (float)h1, (float)h2, vs); \
-        SEM_HIP(hipGetLastError());                                                         \
-        break;                                                                              \
+    // one workgroup per EPB elements (a persistent grid capped at the
+    // resident count, or at 8 per CU, was slower: the last, partial round of
+    // workgroups leaves CUs idle)
+#define SEM_FDM(NE)                                                                                   \
+    case NE: {                                                                                        \
+        const dim3 grid((unsigned)((L.E + FdmShape<NE>::EPB - 1) / FdmShape<NE>::EPB));              \
+        if (ras)                                                                                      \
+            hipLaunchKernelGGL((fdm_kernel<NE, false>), grid, dim3(FdmShape<NE>::THREADS), 0, s, L.E, \
+                               L.sz_ix, L.sz_S, L.sz_lam, r, t, L.nL, acc, U, (float)h1, (float)h2, vs); \
+        else                                                                                          \
+            hipLaunchKernelGGL((fdm_kernel<NE, true>), grid, dim3(FdmShape<NE>::THREADS), 0, s, L.E,  \
+                               L.sz_ix, L.sz_S, L.sz_lam, r, t, L.nL, acc, U, (float)h1, (float)h2, vs); \
+        SEM_HIP(hipGetLastError());                                                                   \
+        break;                                                                                        \
     }
     switch (L.sz_ne) {
         SEM_FDM(5) SEM_FDM(6) SEM_FDM(7) SEM_FDM(8) SEM_FDM(9) SEM_FDM(10) SEM_FDM(11)
@@ -693,7 +719,7 @@ int launch_schwarz(const Level &L, bool ras, const float *r, const float *t, flo
     if (!ras && L.sz_nrc > 0) {
         const int64_t ldU = L.E * (int64_t)L.sz_next;
         const int64_t groups = (L.sz_nrc + 255) / 256;
-        const unsigned g = (unsigned)std::min<int64_t>(groups, cap);
+        const unsigned g = (unsigned)std::min<int64_t>(groups, (int64_t)(L.n_cu > 0 ? L.n_cu : 256) * 8);
         hipLaunchKernelGGL(asm_ext_kernel, dim3(g), dim3(256), 0, s, L.sz_nrc, L.sz_rc,
                            L.sz_off, L.sz_src, (const float *)U, ldU, acc, L.nL, vs);
         SEM_HIP(hipGetLastError());
