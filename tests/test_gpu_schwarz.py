@@ -32,7 +32,8 @@ def _host(t):
 @pytest.mark.parametrize("variant", ["asm", "ras"])
 @pytest.mark.parametrize("shape,N,bc,h2", [((3, 3, 2), 7, "dirichlet", 10.0), ((2, 3, 2), 4, "neumann", 1.0),
                                            ((3, 2, 2), 2, "dirichlet", 0.0), ((2, 2, 3), 8, "dirichlet", 3.0),
-                                           ((1, 1, 1), 5, "dirichlet", 1.0), ((1, 1, 2), 3, "neumann", 2.0)])
+                                           ((1, 1, 1), 5, "dirichlet", 1.0), ((1, 1, 2), 3, "neumann", 2.0),
+                                           ((2, 2, 2), 6, "neumann", 0.5)])
 def test_smoother_apply_matches_oracle(variant, shape, N, bc, h2):
     print(f"[gpu] schwarz apply {variant} {shape} N={N} {bc}", flush=True)
     m = _mesh(shape, N, deform="cyclic", bc=bc)
