@@ -126,14 +126,22 @@ SEM_API int sem_free(sem_handle h);
 SEM_API int sem_ax(sem_handle h, const double *u, double *w, double h1, double h2, const double *k,
            void *stream);
 
+/* gather-scatter reductions (the associative, commutative operations of
+ * gs_op, Sec. 3.2) */
+enum sem_gs_op { SEM_GS_ADD = 0, SEM_GS_MUL = 1, SEM_GS_MIN = 2, SEM_GS_MAX = 3 };
+
 /*
- * Direct-stiffness summation v <- QQ^T v in place (Sec. 2.3 eq. (dssum) and
- * the Q / Q^T discussion; gs_op(+) of Sec. 3.2): every copy of a global node
- * receives the sum over all its copies; copies with pointer 0 or a unique
- * pointer are unchanged.  Each sum adds the copies in ascending local index
- * order, so the result is deterministic.  v: device L-vector, FP64.
+ * Gather-scatter in place (Sec. 3.2, gs_op(gsh, w_L, op)).  With op =
+ * SEM_GS_ADD it is the direct-stiffness summation v <- QQ^T v (Sec. 2.3 eq.
+ * (dssum) and the Q / Q^T discussion): every copy of a global node receives
+ * the sum over all its copies, formed from 0 by adding the copies in
+ * ascending local index order, so the result is deterministic.  SEM_GS_MUL,
+ * SEM_GS_MIN and SEM_GS_MAX give every copy the product, minimum (fmin) or
+ * maximum (fmax) over the node's copies, formed from the first copy in the
+ * same order.  Copies with pointer 0 or a unique pointer are unchanged.
+ * v: device L-vector, FP64.  Another op: SEM_EINVAL.
  */
-SEM_API int sem_gs(sem_handle h, double *v, void *stream);
+SEM_API int sem_gs(sem_handle h, double *v, int op, void *stream);
 
 /*
  * Several fields through the same operator, as the three velocity components

@@ -79,6 +79,7 @@ def _bind(L):
     L.oracle_ax.argtypes = [ctypes.c_int, i64, d, d, d, d, ctypes.c_double, ctypes.c_double, d, d]
     L.oracle_diag.argtypes = [ctypes.c_int, i64, d, d, d, d, ctypes.c_double, ctypes.c_double, d]
     L.oracle_qqt.argtypes = [i64, p64, d]
+    L.oracle_gs_op.argtypes = [i64, p64, ctypes.c_int, d]
     L.oracle_multiplicity.argtypes = [i64, p64, p32]
     L.oracle_gs_maps.argtypes = [i64, p64, p64, p64, p32, p32]
     L.oracle_grad_k.argtypes = [ctypes.c_int, i64, d, d, ctypes.c_double, d, d, d]
@@ -190,6 +191,19 @@ def qqt(gid, v):
     g = np.ascontiguousarray(gid, dtype=np.int64).reshape(-1)
     out = np.array(v, dtype=np.float64).reshape(-1).copy()
     _check(lib().oracle_qqt(g.size, _i64(g), _d(out)), "qqt")
+    return out
+
+
+GS_OPS = {"add": 0, "mul": 1, "min": 2, "max": 3}
+
+
+def gs_op(gid, v, op: str = "add"):
+    """gs_op(gsh, v, op) of Sec. 3.2: every copy of a shared node receives the
+    sum ("add", equal to qqt), product, minimum or maximum of the node's copies
+    in ascending local index order (the last three from the first copy)."""
+    g = np.ascontiguousarray(gid, dtype=np.int64).reshape(-1)
+    out = np.array(v, dtype=np.float64).reshape(-1).copy()
+    _check(lib().oracle_gs_op(g.size, _i64(g), GS_OPS[op], _d(out)), "gs_op")
     return out
 
 

@@ -394,6 +394,48 @@ int oracle_qqt(int64_t nL, const int64_t *gid, double *v)
     return ORC_OK;
 }
 
+/* gs_op of Sec. 3.2 with the library's associative, commutative operations:
+ * op 0 sum (identical to oracle_qqt: from 0, copies in ascending local index
+ * order), 1 product, 2 minimum (fmin), 3 maximum (fmax), the last three started
+ * from the node's first copy and combined with the others in ascending local
+ * index order.  Every copy of a node receives the result; pointer 0 and
+ * unique pointers are left unchanged. */
+int oracle_gs_op(int64_t nL, const int64_t *gid, int op, double *v)
+{
+    if (nL < 0 || !gid || !v || op < 0 || op > 3) return ORC_EINVAL;
+    int64_t *cid = malloc(sizeof(int64_t) * (nL ? nL : 1));
+    if (!cid) return ORC_EINVAL;
+    int64_t ng = compact_ids(nL, gid, cid);
+    if (ng < 0) { free(cid); return (int)ng; }
+    double *acc = calloc(ng ? ng : 1, sizeof(double));
+    unsigned char *seen = calloc(ng ? ng : 1, 1);
+    if (!acc || !seen) { free(acc); free(seen); free(cid); return ORC_EINVAL; }
+    for (int64_t l = 0; l < nL; ++l) {
+        const int64_t c = cid[l];
+        if (c < 0) continue;
+        if (op == 0) {
+            acc[c] += v[l];
+        } else if (!seen[c]) {
+            acc[c] = v[l];
+            seen[c] = 1;
+        } else if (op == 1) {
+            acc[c] = acc[c] * v[l];
+        } else if (op == 2) {
+            acc[c] = fmin(acc[c], v[l]);
+        } else {
+            acc[c] = fmax(acc[c], v[l]);
+        }
+    }
+    for (int64_t l = 0; l < nL; ++l) {
+        const int64_t c = cid[l];
+        if (c >= 0) v[l] = acc[c];
+    }
+    free(seen);
+    free(acc);
+    free(cid);
+    return ORC_OK;
+}
+
 /* Multiplicity of each local copy: number of copies with the same nonzero
  * global pointer (1 for pointer 0). */
 int oracle_multiplicity(int64_t nL, const int64_t *gid, int32_t *mult)

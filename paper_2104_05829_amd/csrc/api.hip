@@ -433,14 +433,18 @@ int sem_ax(sem_handle h, const double *u, double *w, double h1, double h2, const
                              (hipStream_t)stream);
 }
 
-int sem_gs(sem_handle h, double *v, void *stream)
+int sem_gs(sem_handle h, double *v, int op, void *stream)
 {
     SEM_TRY(check_level(h, 0, "sem_gs"));
     if (!v) {
         set_error("sem_gs: null vector");
         return SEM_EINVAL;
     }
-    return launch_gs<double>(h->lv[0], v, (hipStream_t)stream);
+    if (op != SEM_GS_ADD && op != SEM_GS_MUL && op != SEM_GS_MIN && op != SEM_GS_MAX) {
+        set_error("sem_gs: unknown operation %d", op);
+        return SEM_EINVAL;
+    }
+    return launch_gs_op<double>(h->lv[0], v, op, (hipStream_t)stream);
 }
 
 int sem_ax_level(sem_handle h, int level, int dtype, const void *u, void *w, double h1, double h2,

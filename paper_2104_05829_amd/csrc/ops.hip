@@ -28,12 +28,25 @@ __device__ inline int64_t xcd_chunk_block(int64_t b, int64_t nb)
 
 constexpr int kGsWavesPerBlock = 4;
 
+// The reduction of a segment (gs_op of Sec. 3.2): the sum (the direct-
+// stiffness summation QQ^T, started from 0 as the plain definition is), or
+// the product, minimum or maximum of the copies started from the first copy;
+// every form combines the copies in ascending local index order.
+template <int OP, typename T>
+__device__ __forceinline__ T gs_combine(T a, T b)
+{
+    if constexpr (OP == SEM_GS_MUL) return a * b;
+    else if constexpr (OP == SEM_GS_MIN) return fmin(a, b);
+    else if constexpr (OP == SEM_GS_MAX) return fmax(a, b);
+    else return a + b;
+}
+
 // One map load per lane ahead of the values: the chunk's copy list padded to
 // 64 lanes (cperm[c][lane]: the copy, with kGsSegStart set where it starts a
 // segment, or -1 past the chunk's end), so the gathers depend on a single
 // coalesced load; the chunk size and the segment starts follow by ballots.
 // The copy indices are applied to every vector of the batch in turn.
-template <typename T>
+template <typename T, int OP = SEM_GS_ADD>
 __global__ void __launch_bounds__(64 * kGsWavesPerBlock)
 gs_chunk_kernel(int64_t nchunks, const int32_t *__restrict__ cperm, T *__restrict__ v, int64_t ld,
                 VSet vs, const int *__restrict__ skip, int skip_stride)
@@ -66,17 +79,18 @@ gs_chunk_kernel(int64_t nchunks, const int32_t *__restrict__ cperm, T *__restric
 #pragma unroll
     for (int q = 0; q < kMaxRhs; ++q) {
         if (q >= na) break;
-        T acc = T(0);
-        for (int j = 0; j < maxlen; ++j) {  // wave-uniform trip count
+        constexpr int j0 = OP == SEM_GS_ADD ? 0 : 1;
+        T acc = OP == SEM_GS_ADD ? T(0) : __shfl(val[q], s0);
+        for (int j = j0; j < maxlen; ++j) {  // wave-uniform trip count
             const T other = __shfl(val[q], min(s0 + j, 63));
-            if (j < len) acc += other;
+            if (j < len) acc = gs_combine<OP>(acc, other);
         }
         if (act) v[(int64_t)((pack >> (8 * q)) & 255u) * ld + idx] = acc;
     }
 }
 
 // segments listed in `segs`, one thread each (copies in canonical order)
-template <typename T>
+template <typename T, int OP = SEM_GS_ADD>
 __global__ void gs_segment_kernel(int64_t nseg, const int32_t *__restrict__ segs,
                                   const int32_t *__restrict__ perm,
                                   const int32_t *__restrict__ offs, T *__restrict__ v, int64_t ld,
@@ -90,8 +104,8 @@ __global__ void gs_segment_kernel(int64_t nseg, const int32_t *__restrict__ segs
     const int a = offs[sidx], b = offs[sidx + 1];
     for (int q = 0; q < na; ++q) {
         T *vq = v + (int64_t)((pack >> (8 * q)) & 255u) * ld;
-        T acc = T(0);
-        for (int o = a; o < b; ++o) acc += vq[perm[o]];
+        T acc = OP == SEM_GS_ADD ? T(0) : vq[perm[a]];
+        for (int o = OP == SEM_GS_ADD ? a : a + 1; o < b; ++o) acc = gs_combine<OP>(acc, vq[perm[o]]);
         for (int o = a; o < b; ++o) vq[perm[o]] = acc;
     }
 }
@@ -122,6 +136,40 @@ int launch_gs(const Level &L, T *v, hipStream_t s, const int *skip)
 {
     return launch_gs_multi<T>(L, v, 0, VSet::one(), s, skip, 0);
 }
+
+// one field with any gs_op reduction (the solver paths use the sum only)
+template <typename T, int OP>
+static int launch_gs_one_op(const Level &L, T *v, hipStream_t s)
+{
+    const VSet vs = VSet::one();
+    if (L.nchunks > 0) {
+        const int64_t nb = (L.nchunks + kGsWavesPerBlock - 1) / kGsWavesPerBlock;
+        hipLaunchKernelGGL((gs_chunk_kernel<T, OP>), dim3((unsigned)nb), dim3(64 * kGsWavesPerBlock), 0, s,
+                           L.nchunks, L.chunk_perm, v, (int64_t)0, vs, (const int *)nullptr, 0);
+        SEM_HIP(hipGetLastError());
+    }
+    if (L.nover > 0) {
+        const int bs = 256;
+        const int64_t nb = (L.nover + bs - 1) / bs;
+        hipLaunchKernelGGL((gs_segment_kernel<T, OP>), dim3((unsigned)nb), dim3(bs), 0, s, L.nover, L.over,
+                           L.perm, L.offs, v, (int64_t)0, vs, (const int *)nullptr, 0);
+        SEM_HIP(hipGetLastError());
+    }
+    return SEM_OK;
+}
+
+template <typename T>
+int launch_gs_op(const Level &L, T *v, int op, hipStream_t s)
+{
+    switch (op) {
+    case SEM_GS_ADD: return launch_gs<T>(L, v, s, nullptr);
+    case SEM_GS_MUL: return launch_gs_one_op<T, SEM_GS_MUL>(L, v, s);
+    case SEM_GS_MIN: return launch_gs_one_op<T, SEM_GS_MIN>(L, v, s);
+    case SEM_GS_MAX: return launch_gs_one_op<T, SEM_GS_MAX>(L, v, s);
+    default: set_error("gather-scatter: unknown operation %d", op); return SEM_EINVAL;
+    }
+}
+template int launch_gs_op<double>(const Level &, double *, int, hipStream_t);
 template int launch_gs<double>(const Level &, double *, hipStream_t, const int *);
 template int launch_gs<float>(const Level &, float *, hipStream_t, const int *);
 template int launch_gs_multi<double>(const Level &, double *, int64_t, const VSet &, hipStream_t,

@@ -260,6 +260,9 @@ int launch_ax(const Level &L, const T *G, const T *B, const T *D, const T *u, T 
 
 template <typename T>
 int launch_gs(const Level &L, T *v, hipStream_t s, const int *skip = nullptr);
+// one field, any reduction SEM_GS_ADD / MUL / MIN / MAX (SEM_EINVAL otherwise)
+template <typename T>
+int launch_gs_op(const Level &L, T *v, int op, hipStream_t s);
 
 // Batched forms: the vectors of `vs` (vector v at u + v * ldu, w + v * ldw),
 // one launch for the whole batch; the element operator reads each element's

@@ -23,6 +23,7 @@ SEM_F64, SEM_F32 = 0, 1
 SEM_PRECOND_JACOBI, SEM_PRECOND_PMG = 0, 1
 SEM_SMOOTH_JACOBI, SEM_SMOOTH_ASM, SEM_SMOOTH_RAS = 0, 1, 2
 SEM_ADVECT_AUTO, SEM_ADVECT_2D, SEM_ADVECT_3D = 0, 1, 2
+SEM_GS_ADD, SEM_GS_MUL, SEM_GS_MIN, SEM_GS_MAX = 0, 1, 2, 3
 SEM_MAX_RHS = 4
 SEM_MAX_PROJ = 16
 # largest level-0 L-vector of sem_pcg_solve_noalloc (its static scratch)
@@ -86,7 +87,7 @@ _SIGS = {
                                  ctypes.POINTER(_VP)]),
     "sem_free": (ctypes.c_int, [_VP]),
     "sem_ax": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, ctypes.c_double, _VP, _VP]),
-    "sem_gs": (ctypes.c_int, [_VP, _VP, _VP]),
+    "sem_gs": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP]),
     "sem_ax_level": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, _VP, ctypes.c_double,
                                     ctypes.c_double, _VP]),
     "sem_gs_level": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, _VP]),
@@ -311,10 +312,15 @@ class Sem:
         _check(lib().sem_ax(self._handle(), pu, pw, float(h1), float(h2), pk, _stream()), "sem_ax")
         return w
 
-    def gs(self, v):
+    _GS_OPS = {"add": SEM_GS_ADD, "mul": SEM_GS_MUL, "min": SEM_GS_MIN, "max": SEM_GS_MAX}
+
+    def gs(self, v, op="add"):
+        """Gather-scatter in place: op "add" is QQ^T; "mul", "min", "max" give
+        every copy the product / minimum / maximum over its node's copies."""
         torch = _torch()
         pv = _dev_ptr(v, torch.float64, self.n_local, "v")
-        _check(lib().sem_gs(self._handle(), pv, _stream()), "sem_gs")
+        code = self._GS_OPS[op] if isinstance(op, str) else int(op)
+        _check(lib().sem_gs(self._handle(), pv, code, _stream()), "sem_gs")
         return v
 
     def ax_level(self, level, u, w=None, h1=1.0, h2=0.0):

@@ -97,7 +97,7 @@ def test_host_error_paths():
     assert not h.value
     # null handle everywhere
     assert L.sem_ax(None, None, None, 1.0, 0.0, None, None) == S.SEM_EINVAL
-    assert L.sem_gs(None, None, None) == S.SEM_EINVAL
+    assert L.sem_gs(None, None, S.SEM_GS_ADD, None) == S.SEM_EINVAL
     o = S.Sem.default_opts()
     assert L.sem_pcg_solve(None, None, None, ctypes.byref(o), None, None) == S.SEM_EINVAL
     assert L.sem_free(None) == 0
@@ -133,4 +133,9 @@ def test_binding_constants_match_header():
     txt = open(HEADER).read()
     for name in ("SEM_MAX_RHS", "SEM_MAX_PROJ", "SEM_NOALLOC_MAX_LOCAL"):
         m = re.search(r"#define\s+" + name + r"\s+(\d+)", txt)
+        assert m and int(m.group(1)) == getattr(S, name), name
+    for name in ("SEM_F64", "SEM_F32", "SEM_GS_ADD", "SEM_GS_MUL", "SEM_GS_MIN", "SEM_GS_MAX",
+                 "SEM_PRECOND_JACOBI", "SEM_PRECOND_PMG", "SEM_SMOOTH_JACOBI", "SEM_SMOOTH_ASM",
+                 "SEM_SMOOTH_RAS", "SEM_ADVECT_AUTO", "SEM_ADVECT_2D", "SEM_ADVECT_3D"):
+        m = re.search(r"\b" + name + r"\s*=\s*(\d+)", txt)
         assert m and int(m.group(1)) == getattr(S, name), name

@@ -97,6 +97,25 @@ def test_gs_bit_exact(shape, N, iz):
     s.free()
 
 
+@pytest.mark.parametrize("op", ["add", "mul", "min", "max"])
+@pytest.mark.parametrize("shape,N,iz", [((4, 3, 3), 7, False), ((3, 2, 2), 2, True)])
+def test_gs_ops_bit_exact(shape, N, iz, op):
+    """sem_gs with each gs_op reduction (Sec. 3.2: +, *, min, max) against the
+    oracle's gs_op bit for bit (products and sums in ascending local index
+    order; values in +-[0.5, 1.5] so that no product under- or overflows);
+    an unknown op is rejected."""
+    print(f"[gpu] gs op={op} shape={shape} N={N}", flush=True)
+    m = _mesh(shape, N, deform="cyclic", interior_zero=iz)
+    s = Sem(m)
+    rng = np.random.default_rng(17)
+    v = rng.uniform(0.5, 1.5, m.n_local) * rng.choice([-1.0, 1.0], m.n_local)
+    out = _host(s.gs(_dev(v), op=op))
+    np.testing.assert_array_equal(out, oracle.gs_op(m.gid, v, op))
+    with pytest.raises(SemError):
+        s.gs(_dev(v), op=7)
+    s.free()
+
+
 def test_c2_full_size_ax_gs_parity():
     """16^3 deformed box, N=7 (2,097,152 local points), the benchmark's
     configuration and launch: Ax then gs, all outputs against the oracle."""
@@ -414,7 +433,7 @@ def test_grad_k_parity(shape, N):
 def test_gs_nodes_with_more_than_64_copies():
     """80 coincident elements whose nodes share global pointers (80 copies per
     node, beyond one wavefront chunk) plus a second block of ordinary shared
-    nodes: QQ^T stays bit-exact."""
+    nodes: QQ^T and the product, minimum and maximum stay bit-exact."""
     print("[gpu] gs overflow segments", flush=True)
     N = 2
     xi, _ = oracle.gll(N)
@@ -431,6 +450,9 @@ def test_gs_nodes_with_more_than_64_copies():
     v = inputs.uniform_lvector(gid.size, 8)
     out = _host(s.gs(_dev(v)))
     np.testing.assert_array_equal(out, oracle.qqt(gid, v))
+    w = np.random.default_rng(9).uniform(0.5, 1.5, gid.size)
+    for op in ("mul", "min", "max"):
+        np.testing.assert_array_equal(_host(s.gs(_dev(w), op=op)), oracle.gs_op(gid, w, op))
     perm, offs = s.maps()
     po, oo = oracle.gs_maps(gid)
     np.testing.assert_array_equal(_host(perm), po)
@@ -464,12 +486,14 @@ def test_pmg_iterations_match_oracle_pmg(levels):
 
 @pytest.mark.parametrize("precond", ["jacobi", "pmg"])
 def test_vector_and_scalar_kernel_forms_agree(precond):
-    """The Krylov vector kernels move 16 bytes per lane when every array they
-    touch is 16-byte aligned and fall back to one value per lane otherwise
-    (here: the solution at an 8-byte offset).  Both forms do the same
-    arithmetic per point and differ only in the order of their partial sums:
-    iteration counts within one, solutions within 1e-9 of each other, and both
-    within 1e-8 of the oracle's tight solve."""
+    """The flexible-CG vector kernels of the p-MG solve move 16 bytes per lane
+    when every array they touch is 16-byte aligned and fall back to one value
+    per lane otherwise (here: the solution at an 8-byte offset).  Both forms do
+    the same arithmetic per point and differ only in the order of their partial
+    sums: iteration counts within one, solutions within 1e-9 of each other, and
+    both within 1e-8 of the oracle's tight solve.  The Jacobi-PCG kernels have
+    the one-value form only, so there the offset solution must leave the solve
+    unchanged bit for bit."""
     print(f"[gpu] vector vs scalar kernel forms {precond}", flush=True)
     N = 7
     m = _mesh((3, 3, 2), N, deform="cyclic")
@@ -487,6 +511,8 @@ def test_vector_and_scalar_kernel_forms_agree(precond):
     assert rca == 0 and rcm == 0
     assert abs(sa["iters"] - sm["iters"]) <= 1, (sa, sm)
     ha, hm = _host(xa), _host(xm)
+    if precond == "jacobi":
+        assert sa["iters"] == sm["iters"] and np.array_equal(ha, hm)
     wn = lambda v: np.sqrt(np.sum(lv.W * v ** 2))  # noqa: E731
     assert wn(ha - hm) <= 1e-9 * wn(ha)
     xo, _, _ = solvers.pcg_jacobi(lv, b, tol=1e-13)

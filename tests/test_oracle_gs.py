@@ -87,3 +87,71 @@ def test_qqt_sums_in_ascending_local_order():
     perm, offs = oracle.gs_maps(g)
     np.testing.assert_array_equal(perm, [1, 5, 0, 2, 4])
     np.testing.assert_array_equal(offs, [0, 2, 5])
+
+
+def _gs_op_brute(g, v, op):
+    """gs_op by a dictionary walk in ascending local index order (the
+    definition, written independently of the oracle's compact-id loop)."""
+    out = v.copy()
+    nodes = {}
+    for l, p in enumerate(g):
+        if p != 0:
+            nodes.setdefault(int(p), []).append(l)
+    for idx in nodes.values():
+        if len(idx) < 2:
+            continue
+        if op == "add":
+            r = 0.0
+            for l in idx:
+                r = r + v[l]
+        else:
+            r = v[idx[0]]
+            for l in idx[1:]:
+                r = r * v[l] if op == "mul" else (min(r, v[l]) if op == "min" else max(r, v[l]))
+        for l in idx:
+            out[l] = r
+    return out
+
+
+@pytest.mark.parametrize("op", ["add", "mul", "min", "max"])
+def test_gs_op_brute_force_and_invariants(op):
+    """gs_op with each of the library's operations (Sec. 3.2: min, max, *, +)
+    against a brute-force walk on a small mesh with singletons and a renumbered
+    unique copy; the result is constant over a node's copies and lies in
+    [min, max] of them; the sum equals QQ^T bit for bit."""
+    xi, _ = oracle.gll(2)
+    m = inputs.box_mesh(3, 2, 2, xi, interior_zero=True)
+    g = m.gid.reshape(-1).copy()
+    g[7] = 10 ** 9
+    v = np.random.default_rng(3).uniform(0.5, 1.5, g.size) * np.where(np.arange(g.size) % 3 == 0, -1.0, 1.0)
+    out = oracle.gs_op(g, v, op)
+    np.testing.assert_array_equal(out, _gs_op_brute(g, v, op))
+    assert out[7] == v[7]
+    np.testing.assert_array_equal(out[g == 0], v[g == 0])
+    for p in np.unique(g[g != 0]):
+        sel = g == p
+        assert np.all(out[sel] == out[sel][0])
+        if op in ("min", "max") and sel.sum() > 1:
+            assert v[sel].min() <= out[sel][0] <= v[sel].max()
+            assert out[sel][0] == (v[sel].min() if op == "min" else v[sel].max())
+    if op == "add":
+        np.testing.assert_array_equal(out, oracle.qqt(g, v))
+
+
+def test_gs_op_order_and_closed_forms():
+    """Products in ascending local index order (rounding differs from the
+    reverse order on this input); min/max of a node with a NaN copy follow
+    fmin/fmax (the NaN is ignored); the product of 2^k over k copies is
+    2^(k(k+1)/2) exactly."""
+    g = np.array([4, 4, 4, 9, 9, 0], dtype=np.int64)
+    a, b, c = float.fromhex("0x1.8f91bc9a1fc12p-1"), float.fromhex("0x1.f86af38eff19fp-1"), float.fromhex("0x1.7b1197d71defap+0")
+    assert (a * b) * c != (c * b) * a
+    v = np.array([a, b, c, np.nan, 2.5, -1.0])
+    mul = oracle.gs_op(g, v, "mul")
+    assert mul[0] == mul[1] == mul[2] == (a * b) * c
+    assert oracle.gs_op(g, v, "min")[3] == 2.5 and oracle.gs_op(g, v, "max")[4] == 2.5
+    assert oracle.gs_op(g, v, "min")[5] == -1.0
+    k = 6
+    gp = np.full(k, 5, dtype=np.int64)
+    vp = 2.0 ** np.arange(1, k + 1, dtype=np.float64)
+    np.testing.assert_array_equal(oracle.gs_op(gp, vp, "mul"), np.full(k, 2.0 ** (k * (k + 1) // 2)))

@@ -60,6 +60,9 @@ MUTANTS = [
      "s += J[k * ns + c] * J[j * ns + b] * J[a * nt + i]"),
     ("interp_lvec_element_stride", "* in[e * pin + a + ns * (b + ns * c)];",
      "* in[e * pout % (pin * E) + a + ns * (b + ns * c)];"),
+    ("gsop_min_as_max", "acc[c] = fmin(acc[c], v[l]);", "acc[c] = fmax(acc[c], v[l]);"),
+    ("gsop_first_copy_dropped", "acc[c] = v[l];\n            seen[c] = 1;", "acc[c] = 1.0;\n            seen[c] = 1;"),
+    ("gsop_mul_as_add", "acc[c] = acc[c] * v[l];", "acc[c] = acc[c] + v[l];"),
 ]
 
 PINS = [
@@ -80,6 +83,9 @@ PINS = [
     lambda gd: t_gs.test_multiplicity_and_maps((3, 2, 1), 3),
     lambda gd: t_gs.test_qqt_dense_and_contract(),
     lambda gd: t_gs.test_qqt_sums_in_ascending_local_order(),
+    lambda gd: t_gs.test_gs_op_brute_force_and_invariants("mul"),
+    lambda gd: t_gs.test_gs_op_brute_force_and_invariants("min"),
+    lambda gd: t_gs.test_gs_op_order_and_closed_forms(),
     lambda gd: t_sol.test_pcg_matches_dense_cholesky(0.0),
     lambda gd: t_adj.test_adjoint_gradients_vs_central_differences(),
 ]
@@ -98,7 +104,7 @@ def _swap_in(so):
     L = ctypes.CDLL(so)
     ref = oracle.lib()
     for fn in ("oracle_gll", "oracle_dhat", "oracle_interp", "oracle_geometry", "oracle_ax",
-               "oracle_diag", "oracle_qqt", "oracle_multiplicity", "oracle_gs_maps",
+               "oracle_diag", "oracle_qqt", "oracle_gs_op", "oracle_multiplicity", "oracle_gs_maps",
                "oracle_grad_k", "oracle_interp_lvec"):
         getattr(L, fn).argtypes = getattr(ref, fn).argtypes
     return L
