@@ -43,6 +43,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6  # MI355X dense FP64 (vector and matrix)
 AX_BYTES_PER_POINT = 64  # u 8 + six G 48 + w 8 (FP64 Poisson)
 AX3_BYTES_PER_POINT = 96  # three fields: 3 x (u 8 + w 8) + six G 48 read once
+AX32_BYTES_PER_POINT = 32  # FP32 Poisson: u 4 + six G 24 + w 4
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "ax_fp64_box16_n7_traffic.txt")
 AX_SOURCE = os.path.join(ROOT, "paper_2104_05829_amd", "csrc", "ax_impl.h")
 
@@ -161,9 +162,56 @@ def bench_operator(args, torch, sem_mod, inputs):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_ax3 = ev0.elapsed_time(ev1) / args.steps
+    # per-step HIP-event times (median and mean), separately from the timed loop above
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for a, b_ in evs:
+        a.record(stream)
+        s.ax(u, w)
+        s.gs(w)
+        b_.record(stream)
+    torch.cuda.synchronize()
+    per_step = sorted(a.elapsed_time(b_) for a, b_ in evs)
     s.free()
+    # the FP32 form of the same step (the smoother's precision): level 0 of a
+    # p-MG handle, sem_ax_level + sem_gs_level in FP32
+    s32 = sem_mod.Sem(mesh, levels=(7, 3, 1))
+    u32 = u.float()
+    w32 = torch.empty_like(u32)
+    for _ in range(args.warmup):
+        s32.ax_level(0, u32, w32)
+        s32.gs_level(0, w32)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        s32.ax_level(0, u32, w32)
+        s32.gs_level(0, w32)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_step32 = ev0.elapsed_time(ev1) / args.steps
+    ev0.record(stream)
+    for _ in range(args.steps):
+        s32.ax_level(0, u32, w32)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_ax32 = ev0.elapsed_time(ev1) / args.steps
+    s32.free()
+    del u32, w32
+    # a plain device copy of 1 GiB (torch), the measured stream reference
+    x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    ev0.record(stream)
+    for _ in range(10):
+        y.copy_(x)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * x.numel() * 8 / (ev0.elapsed_time(ev1) / 10 * 1e-3) / 1e9
+    del x, y
     return dict(mesh=mesh, nL=nL, nU=nU, ms_step=ms_step, ms_ax=ms_ax, ms_gs=ms_gs, ms_ax3=ms_ax3,
-                n_shared=inf["n_shared_copies"], n_seg=inf["n_segments"])
+                n_shared=inf["n_shared_copies"], n_seg=inf["n_segments"],
+                ms_step_median=per_step[len(per_step) // 2], ms_step_mean=sum(per_step) / len(per_step),
+                ms_step32=ms_step32, ms_ax32=ms_ax32, copy_gbs=copy_gbs)
 
 
 def bench_pcg(args, torch, sem_mod, inputs):
@@ -773,6 +821,19 @@ def main():
             "E": 4096, "N": 7, "n_local": op["nL"], "n_unique": op["nU"],
             "gdof_local_per_s": round(op["nL"] / (op["ms_step"] * 1e-3) / 1e9, 3),
             "ms_ax": round(op["ms_ax"], 5), "ms_gs": round(op["ms_gs"], 5),
+            "ms_step_events_median": round(op["ms_step_median"], 5),
+            "ms_step_events_mean": round(op["ms_step_mean"], 5),
+        },
+        "fp32_step": {
+            "call": "sem_ax_level + sem_gs_level, level 0 in FP32 (the smoother precision), same mesh",
+            "ms_step": round(op["ms_step32"], 5), "ms_ax": round(op["ms_ax32"], 5),
+            "gdof_per_s": round(op["nU"] / (op["ms_step32"] * 1e-3) / 1e9, 3),
+            "ax_algorithmic_GBps": round(AX32_BYTES_PER_POINT * op["nL"] / (op["ms_ax32"] * 1e-3) / 1e9, 1),
+        },
+        "stream_copy": {
+            "call": "torch copy of 1 GiB FP64 (1 GiB read + 1 GiB written), HIP events",
+            "GBps": round(op["copy_gbs"], 1), "frac_hbm_peak": round(op["copy_gbs"] / HBM_PEAK_GBS, 4),
+            "ax_frac_of_copy": round(achieved / op["copy_gbs"], 4),
         },
         "ax_three_fields": {
             "call": "sem_ax_multi, 3 FP64 fields, G read once per element",
