@@ -567,10 +567,13 @@ def bench_large(args, torch, sem_mod, inputs):
     mesh = sem_mod.box_mesh(64, 64, 32, N, L=(2.0, 2.0, 1.0), deform="cyclic", amp=0.05,
                             bc="dirichlet")
     t_mesh = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
     t0 = time.perf_counter()
     s = sem_mod.Sem(mesh, levels=(7, 3, 1))
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
+    free_setup = torch.cuda.mem_get_info()[0]
     f = torch.tensor(inputs.gaussian_per_node(mesh.gid, 50), device="cuda")
     b = s.rhs(f)
     del f
@@ -614,6 +617,14 @@ def bench_large(args, torch, sem_mod, inputs):
                                      ("ms_solve", "ms_ax", "ms_gs", "ms_vec", "ms_prec", "ms_coarse")}
         xs[pre] = x.cpu().numpy()
         del x
+    torch.cuda.synchronize()
+    free_solved = torch.cuda.mem_get_info()[0]
+    out["device_memory_GB"] = {
+        "handle_after_setup": round((free0 - free_setup) / 1e9, 2),
+        "with_rhs_and_solver_workspaces": round((free0 - free_solved) / 1e9, 2),
+        "hbm_total": round(torch.cuda.mem_get_info()[1] / 1e9, 1),
+        "note": "device free-memory differences around setup and the two solves (library "
+                "allocations plus torch's cached tensors)"}
     W, _ = s.weights()
     Wh = W.cpu().numpy()
     dx = xs["pmg"] - xs["jacobi"]
@@ -719,10 +730,11 @@ def bench_adjoint(args, torch, sem_mod, inputs):
     fd_k = (Lval(ff, kk + h * dk) - Lval(ff, kk - h * dk)) / (2 * h)
     an_f, an_k = float(torch.dot(gf, d)), float(torch.dot(gk, dk))
     s.free()
-    return {"workload": "8x8x8 deformed box, N=7, variable-coefficient Poisson, loss 1/2||u-u_t||_B^2",
-            "ms_forward_backward": round(ms, 2), "loss": L,
-            "fd_rel_discrepancy_f": float(f"{abs(fd_f - an_f) / abs(an_f):.3e}"),
-            "fd_rel_discrepancy_k": float(f"{abs(fd_k - an_k) / abs(an_k):.3e}")}
+    out = {"workload": "8x8x8 deformed box, N=7, variable-coefficient Poisson, loss 1/2||u-u_t||_B^2",
+           "ms_forward_backward": round(ms, 2), "loss": L,
+           "fd_rel_discrepancy_f": float(f"{abs(fd_f - an_f) / abs(an_f):.3e}"),
+           "fd_rel_discrepancy_k": float(f"{abs(fd_k - an_k) / abs(an_k):.3e}")}
+    return out
 
 
 def cpu_baseline(mesh, seconds):
