@@ -23,6 +23,7 @@ void set_error(const char *fmt, ...)
 static void free_level(Level &L)
 {
     free_schwarz(L);
+    free_coarse_csr(L);
     void *ptrs[] = {L.G, L.B, L.G32, L.B32, L.W, L.W32, L.gid, L.dir, L.perm, L.offs,
                     L.chunk_perm, L.over,
                     L.D, L.D32, L.Jc, L.Jc32, L.Dinv, L.Dinv32};

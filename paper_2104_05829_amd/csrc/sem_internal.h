@@ -151,6 +151,15 @@ struct Level {
     int32_t *sz_rc = nullptr, *sz_off = nullptr, *sz_src = nullptr;
     float *sz_w = nullptr;
     double sz_lmax = 0.0;  // lambda_max(M^{-1} A) estimate for the current key
+    // the coarsest level's operator assembled on its free unique nodes (built
+    // per (h1, h2) with the p-multigrid preconditioner): CSR cs_row [nf+1],
+    // cs_col / cs_val [nnz], inverse diagonal cs_dinv and unit weights cs_one
+    // [nf]; cs_uid [nL] the free node of each copy (-1 on Dirichlet copies),
+    // cs_rep [nf] one copy of each node; cs_bu / cs_xu [kMaxRhs][nf] the
+    // right-hand sides and solutions of the coarse solves on these nodes
+    int64_t cs_nf = 0, cs_nnz = 0;
+    int32_t *cs_row = nullptr, *cs_col = nullptr, *cs_uid = nullptr, *cs_rep = nullptr;
+    double *cs_val = nullptr, *cs_dinv = nullptr, *cs_one = nullptr, *cs_bu = nullptr, *cs_xu = nullptr;
 };
 
 // Phase timers of a solve (sem_solve_opts.timers): a chain of events on the
@@ -328,6 +337,7 @@ __host__ __device__ inline int schwarz_ext_slot(int ne, int a, int b, int c)
 // applies QQ^T and the weight (sz_w for ASM, W32 for RAS).
 int build_schwarz(Level &L, hipStream_t s);
 void free_schwarz(Level &L);
+void free_coarse_csr(Level &L);
 void free_advect(sem_handle h);
 int launch_schwarz(const Level &L, bool ras, const float *r, const float *t, float *U, float *acc,
                    const VSet &vs, double h1, double h2, hipStream_t s);

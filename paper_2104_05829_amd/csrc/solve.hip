@@ -1304,6 +1304,257 @@ static int pcg_start(const Level &L, const VSet &vs, const double *k, double h1,
     return SEM_OK;
 }
 
+// ------------------------------------------------- assembled coarse operator
+// The coarsest level (N = 1 in the default schedule) is small: its operator is
+// assembled once per (h1, h2) on the free unique nodes, and the coarse
+// Jacobi-PCG runs on those nodes with a sparse product instead of the
+// matrix-free operator and QQ^T on the element copies.  Mathematically the
+// same iteration (the assembled matrix is Q^T A_L Q restricted to the free
+// nodes, its diagonal the assembled diagonal); the vectors are 1/multiplicity
+// the length, and one launch (the product) replaces two.
+
+void free_coarse_csr(Level &L)
+{
+    void *ptrs[] = {L.cs_row, L.cs_col, L.cs_uid, L.cs_rep, L.cs_val, L.cs_dinv, L.cs_one, L.cs_bu, L.cs_xu};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    L.cs_row = L.cs_col = L.cs_uid = L.cs_rep = nullptr;
+    L.cs_val = L.cs_dinv = L.cs_one = L.cs_bu = L.cs_xu = nullptr;
+    L.cs_nf = L.cs_nnz = 0;
+}
+
+// u[i] = 1 at local point p of every element, 0 elsewhere
+__global__ void unit_point_kernel(int64_t n, int np, int pt, double *__restrict__ u)
+{
+    GRID_LOOP(i, n) u[i] = (i % np == pt) ? 1.0 : 0.0;
+}
+
+// bu[i] = b[rep[i]] (b assembled: every copy of a node holds its value)
+__global__ void csr_gather_kernel(int64_t nf, VSet vs, int64_t ldb, const int32_t *__restrict__ rep,
+                                  const double *__restrict__ b, int64_t ldu, double *__restrict__ bu)
+{
+    const int64_t v = vsel(vs);
+    b += v * ldb;
+    bu += v * ldu;
+    GRID_LOOP(i, nf) bu[i] = b[rep[i]];
+}
+
+// x[l] = xu[uid[l]] on free copies, 0 on Dirichlet copies
+__global__ void csr_scatter_kernel(int64_t n, VSet vs, const int32_t *__restrict__ uid,
+                                   const double *__restrict__ xu, int64_t ldu, double *__restrict__ x,
+                                   int64_t ldx)
+{
+    const int64_t v = vsel(vs);
+    xu += v * ldu;
+    x += v * ldx;
+    GRID_LOOP(l, n) {
+        const int32_t i = uid[l];
+        x[l] = i >= 0 ? xu[i] : 0.0;
+    }
+}
+
+// y = A p on the free nodes and the partials of (p, y), kCsrLanes lanes per
+// row (entries lane, lane + kCsrLanes, ... of the row, then a fixed butterfly
+// over the lanes, whose first lane keeps the row's value), so every run adds
+// in the same order.  Vectors flagged done are skipped.
+constexpr int kCsrLanes = 8;
+
+__global__ void csr_spmv_dot_kernel(int64_t nf, VSet vs, int64_t ld, const int32_t *__restrict__ row,
+                                    const int32_t *__restrict__ col, const double *__restrict__ val,
+                                    const double *__restrict__ p, double *__restrict__ y,
+                                    double *__restrict__ partial, int64_t pst,
+                                    const KrylovScalars *__restrict__ sc)
+{
+    const int64_t v = vsel(vs);
+    if (sc[v].done) return;
+    p += v * ld;
+    y += v * ld;
+    const int sub = threadIdx.x % kCsrLanes;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x / kCsrLanes;
+    double s[1] = {0.0};
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kCsrLanes; r < nf; r += stride) {
+        const int32_t a = row[r], b = row[r + 1];
+        double acc = 0.0;
+        for (int32_t k = a + sub; k < b; k += kCsrLanes) acc += val[k] * p[col[k]];
+        acc += __shfl_xor(acc, 4, kCsrLanes);
+        acc += __shfl_xor(acc, 2, kCsrLanes);
+        acc += __shfl_xor(acc, 1, kCsrLanes);
+        if (sub == 0) {
+            y[r] = acc;
+            s[0] += p[r] * acc;
+        }
+    }
+    block_sum_store<1>(s, partial + v * pst);
+}
+
+// Assemble the coarsest level's operator h1 A + h2 B on its free unique
+// nodes: the element matrices come from the level's own element operator
+// applied to the unit vector of each local point (all elements at once),
+// then the host adds them into rows by global pointer in element order.
+static int build_coarse_csr(sem_handle h, double h1, double h2, hipStream_t s)
+{
+    Level &L = h->lv[h->n_levels - 1];
+    free_coarse_csr(L);
+    const int np = L.np;
+    const int64_t E = L.E, n = L.nL;
+    if ((int64_t)np * np * E > ((int64_t)1 << 31) - 1) {
+        set_error("coarse operator: too many element-matrix entries (%lld)", (long long)((int64_t)np * np * E));
+        return SEM_EINVAL;
+    }
+    std::vector<double> Ae((size_t)E * np * np), hw((size_t)n);
+    double *u = nullptr, *wv = nullptr;
+    int rc = SEM_OK;
+    if (hipMalloc(&u, sizeof(double) * n) != hipSuccess || hipMalloc(&wv, sizeof(double) * n) != hipSuccess) {
+        set_error("coarse operator: allocation failed");
+        rc = SEM_ENOMEM;
+    }
+    for (int pt = 0; pt < np && rc == SEM_OK; ++pt) {
+        hipLaunchKernelGGL(unit_point_kernel, dim3(red_grid(n)), dim3(kRB), 0, s, n, np, pt, u);
+        if (hipGetLastError() != hipSuccess) rc = SEM_EHIP;
+        if (rc == SEM_OK) rc = launch_ax<double>(L, L.G, L.B, L.D, u, wv, h1, h2, nullptr, nullptr, nullptr, s);
+        if (rc == SEM_OK && (hipMemcpyAsync(hw.data(), wv, sizeof(double) * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                             hipStreamSynchronize(s) != hipSuccess))
+            rc = SEM_EHIP;
+        if (rc == SEM_OK)
+            for (int64_t e = 0; e < E; ++e)
+                for (int q = 0; q < np; ++q) Ae[((size_t)e * np + q) * np + pt] = hw[(size_t)e * np + q];
+    }
+    if (u) (void)hipFree(u);
+    if (wv) (void)hipFree(wv);
+    if (rc != SEM_OK) {
+        if (rc == SEM_EHIP) set_error("coarse operator: %s", hipGetErrorString(hipGetLastError()));
+        return rc;
+    }
+    // free unique nodes, numbered by first copy
+    std::vector<int64_t> gid((size_t)n);
+    std::vector<double> W((size_t)n);
+    SEM_HIP(hipMemcpyAsync(gid.data(), L.gid, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipMemcpyAsync(W.data(), L.W, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> order((size_t)n);
+    for (int64_t l = 0; l < n; ++l) order[l] = l;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return gid[a] < gid[b]; });
+    std::vector<int32_t> uid((size_t)n, -1), rep;
+    {
+        // first copy of each pointer (pointer 0: every copy its own node)
+        std::vector<int64_t> first((size_t)n, -1);
+        for (int64_t i = 0; i < n;) {
+            int64_t j = i;
+            while (j < n && gid[order[j]] == gid[order[i]] && gid[order[i]] != 0) ++j;
+            if (j == i) j = i + 1;
+            for (int64_t k = i; k < j; ++k) first[order[k]] = order[i];
+            i = j;
+        }
+        for (int64_t l = 0; l < n; ++l) {
+            if (!(W[l] > 0.0)) continue;  // Dirichlet copy
+            if (first[l] == l) {
+                uid[l] = (int32_t)rep.size();
+                rep.push_back((int32_t)l);
+            }
+        }
+        for (int64_t l = 0; l < n; ++l)
+            if (W[l] > 0.0) uid[l] = uid[first[l]];
+    }
+    const int64_t nf = (int64_t)rep.size();
+    // entries (row, col) in element order, then summed per (row, col) in that order
+    struct Ent {
+        int32_t r, c;
+        int64_t k;  // position in element order
+    };
+    std::vector<Ent> ent;
+    ent.reserve((size_t)E * np * np);
+    for (int64_t e = 0; e < E; ++e)
+        for (int q = 0; q < np; ++q) {
+            const int32_t rq = uid[(size_t)e * np + q];
+            if (rq < 0) continue;
+            for (int pt = 0; pt < np; ++pt) {
+                const int32_t cp = uid[(size_t)e * np + pt];
+                if (cp < 0) continue;
+                ent.push_back(Ent{rq, cp, ((int64_t)e * np + q) * np + pt});
+            }
+        }
+    std::sort(ent.begin(), ent.end(), [](const Ent &a, const Ent &b) {
+        return a.r != b.r ? a.r < b.r : (a.c != b.c ? a.c < b.c : a.k < b.k);
+    });
+    std::vector<int32_t> row((size_t)nf + 1, 0), col;
+    std::vector<double> val, dinv((size_t)nf, 0.0), one((size_t)nf, 1.0);
+    for (size_t i = 0; i < ent.size();) {
+        size_t j = i;
+        double sum = 0.0;
+        while (j < ent.size() && ent[j].r == ent[i].r && ent[j].c == ent[i].c) sum += Ae[(size_t)ent[j++].k];
+        col.push_back(ent[i].c);
+        val.push_back(sum);
+        ++row[(size_t)ent[i].r + 1];
+        if (ent[i].r == ent[i].c) dinv[(size_t)ent[i].r] = sum;
+        i = j;
+    }
+    for (int64_t r = 0; r < nf; ++r) {
+        row[(size_t)r + 1] += row[(size_t)r];
+        if (!(dinv[(size_t)r] > 0.0)) {
+            set_error("coarse operator: nonpositive diagonal at node %lld", (long long)r);
+            return SEM_EBREAKDOWN;
+        }
+        dinv[(size_t)r] = 1.0 / dinv[(size_t)r];
+    }
+    auto up = [&](void **dst, const void *src, size_t bytes) -> int {
+        SEM_HIP(hipMalloc(dst, bytes > 0 ? bytes : 8));
+        if (bytes && src) SEM_HIP(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, s));
+        return SEM_OK;
+    };
+    int r2 = SEM_OK;
+    if (r2 == SEM_OK) r2 = up((void **)&L.cs_row, row.data(), sizeof(int32_t) * row.size());
+    if (r2 == SEM_OK) r2 = up((void **)&L.cs_col, col.data(), sizeof(int32_t) * col.size());
+    if (r2 == SEM_OK) r2 = up((void **)&L.cs_val, val.data(), sizeof(double) * val.size());
+    if (r2 == SEM_OK) r2 = up((void **)&L.cs_dinv, dinv.data(), sizeof(double) * dinv.size());
+    if (r2 == SEM_OK) r2 = up((void **)&L.cs_one, one.data(), sizeof(double) * one.size());
+    if (r2 == SEM_OK) r2 = up((void **)&L.cs_uid, uid.data(), sizeof(int32_t) * uid.size());
+    if (r2 == SEM_OK) r2 = up((void **)&L.cs_rep, rep.data(), sizeof(int32_t) * rep.size());
+    if (r2 == SEM_OK) r2 = up((void **)&L.cs_bu, nullptr, sizeof(double) * nf * kMaxRhs);
+    if (r2 == SEM_OK) r2 = up((void **)&L.cs_xu, nullptr, sizeof(double) * nf * kMaxRhs);
+    if (r2 == SEM_OK && hipStreamSynchronize(s) != hipSuccess) r2 = SEM_EHIP;
+    if (r2 != SEM_OK) {
+        free_coarse_csr(L);
+        return r2;
+    }
+    L.cs_nf = nf;
+    L.cs_nnz = (int64_t)col.size();
+    return SEM_OK;
+}
+
+// the coarse Jacobi-PCG on the assembled free-node system for the batch vs:
+// b the assembled coarse right-hand sides (L-vectors, leading dimension n),
+// the solutions scattered back into x (L-vectors, 0 on Dirichlet copies)
+static int coarse_csr_solve(sem_handle h, const Level &L, const VSet &vs, const double *b, double *x,
+                            const SolveCfg &cfg, hipStream_t s)
+{
+    Workspace &w = h->ws;
+    const int64_t n = L.nL, nf = L.cs_nf;
+    LAUNCH_B(csr_gather_kernel, nf, vs, s, nf, vs, n, (const int32_t *)L.cs_rep, b, nf, L.cs_bu);
+    const KrylovVecs kv{L.cs_xu, nf, w.c_r, w.c_p, w.c_w, w.sc_c};
+    LAUNCH_B(fill_kernel<double>, nf, vs, s, nf, vs, nf, kv.x, 0.0);
+    LAUNCH_B(pcg_init_kernel, nf, vs, s, nf, vs, nf, (const double *)L.cs_bu, nf, (const double *)nullptr,
+             (const double *)L.cs_dinv, (const double *)L.cs_one, kv.r, kv.p, (float *)nullptr, w.partial,
+             w.pst, 1);
+    LAUNCH_1B(fin_init_kernel, vs, s, vs, (const double *)w.partial, w.pst, (int64_t)red_grid(nf), kv.sc,
+              cfg.coarse_tol, cfg.coarse_maxit, BbRef{});
+    const int nbv = red_grid(nf);
+    const int nbax = red_grid(nf * kCsrLanes);
+    for (int it = 1; it <= cfg.coarse_maxit; ++it) {
+        const int parity = (it - 1) & 1;
+        LAUNCH_B(csr_spmv_dot_kernel, nf * kCsrLanes, vs, s, nf, vs, nf, (const int32_t *)L.cs_row,
+                 (const int32_t *)L.cs_col, (const double *)L.cs_val, (const double *)kv.p, kv.w,
+                 w.partial_ax, w.pst_ax, (const KrylovScalars *)kv.sc);
+        LAUNCH_B(pcg_update_fused_kernel, nf, vs, s, nf, vs, nf, kv.ldx, kv.sc, parity,
+                 (const double *)w.partial_ax, w.pst_ax, (int64_t)nbax, (const double *)kv.p,
+                 (const double *)kv.w, (const double *)L.cs_dinv, (const double *)L.cs_one, kv.x, kv.r,
+                 w.partial, w.pst);
+        LAUNCH_B(pcg_p_fused_kernel, nf, vs, s, nf, vs, nf, kv.sc, parity, it, (const double *)w.partial,
+                 w.pst, (int64_t)nbv, (const double *)L.cs_dinv, (const double *)kv.r, kv.p);
+    }
+    LAUNCH_B(csr_scatter_kernel, n, vs, s, n, vs, (const int32_t *)L.cs_uid, (const double *)L.cs_xu, nf, x, n);
+    return SEM_OK;
+}
+
 // one V-cycle from level l for the batch vs: right-hand sides in mg_r[l]
 // (FP32; FP64 on the coarsest), output in mg_x[l], arrays [nv][nL of level l]
 static int vcycle(sem_handle h, int l, const VSet &vs, const SolveCfg &cfg, hipStream_t s)
@@ -1314,8 +1565,13 @@ static int vcycle(sem_handle h, int l, const VSet &vs, const SolveCfg &cfg, hipS
     const int64_t n = L.nL;
     if (l == lc) {
         double *b = (double *)w.mg_r[l];
-        const KrylovVecs kv{(double *)w.mg_x[l], n, w.c_r, w.c_p, w.c_w, w.sc_c};
         SEM_TRY(clock_mark(w, kPhasePrec, s));
+        if (L.cs_row) {
+            SEM_TRY(coarse_csr_solve(h, L, vs, b, (double *)w.mg_x[l], cfg, s));
+            SEM_TRY(clock_mark(w, kPhaseCoarse, s));
+            return SEM_OK;
+        }
+        const KrylovVecs kv{(double *)w.mg_x[l], n, w.c_r, w.c_p, w.c_w, w.sc_c};
         const PcgBufs pb = ws_bufs(h, L);
         SEM_TRY(pcg_start(L, vs, nullptr, cfg.h1, cfg.h2, b, n, kv, pb, true, cfg.coarse_tol,
                           cfg.coarse_maxit, BbRef{}, s));
@@ -1437,8 +1693,10 @@ static uint64_t vcycle_sig(sem_handle h, const VSet &vs, const SolveCfg &cfg)
         const void *lp[] = {w.mg_r[l], w.mg_x[l], w.mg_t[l], w.mg_d[l], w.mg_s[l], w.sz_acc[l],
                             L.G, L.B, L.G32, L.B32, L.D, L.D32, L.W, L.W32, L.Jc, L.Jc32, L.Dinv,
                             L.Dinv32, L.chunk_perm, L.over, L.perm, L.offs, L.sz_ix, L.sz_S, L.sz_lam,
-                            L.sz_rc, L.sz_off, L.sz_src, L.sz_w};
+                            L.sz_rc, L.sz_off, L.sz_src, L.sz_w, L.cs_row, L.cs_col, L.cs_val, L.cs_dinv,
+                            L.cs_one, L.cs_uid, L.cs_rep, L.cs_bu, L.cs_xu};
         for (const void *p : lp) f.add(p);
+        f.add(L.cs_nf);
         f.add(L.lmax);
         f.add(L.sz_lmax);
         f.add(L.nchunks);
@@ -1711,6 +1969,7 @@ static int prepare_precond(sem_handle h, const sem_solve_opts *o, const SolveCfg
         if (pmg) {
             for (int l = 1; l < h->n_levels; ++l)
                 SEM_TRY(compute_dinv(h, l, nullptr, o->h1, o->h2, l < h->n_levels - 1, s));
+            SEM_TRY(build_coarse_csr(h, o->h1, o->h2, s));
             for (int l = 0; l + 1 < h->n_levels; ++l) {
                 if (cfg.smoother == SEM_SMOOTH_JACOBI)
                     SEM_TRY(lanczos_lmax(h, l, o->h1, o->h2, std::max(2, o->lanczos_steps), &h->lv[l].lmax, s));
