@@ -1529,28 +1529,39 @@ static int coarse_csr_solve(sem_handle h, const Level &L, const VSet &vs, const 
 {
     Workspace &w = h->ws;
     const int64_t n = L.nL, nf = L.cs_nf;
-    LAUNCH_B(csr_gather_kernel, nf, vs, s, nf, vs, n, (const int32_t *)L.cs_rep, b, nf, L.cs_bu);
+    // the vectors are short: one entry per thread where the partial buffers
+    // allow, so each kernel is a single round of memory accesses
+    const int nbv = (int)std::max<int64_t>(1, std::min<int64_t>((nf + kRB - 1) / kRB, kMaxRedBlocks));
+#define LAUNCH_NB(kern, ...)                                                                     \
+    do {                                                                                         \
+        hipLaunchKernelGGL(kern, dim3((unsigned)nbv, (unsigned)vs.n), dim3(kRB), 0, s, __VA_ARGS__); \
+        SEM_HIP(hipGetLastError());                                                              \
+    } while (0)
+    LAUNCH_NB(csr_gather_kernel, nf, vs, n, (const int32_t *)L.cs_rep, b, nf, L.cs_bu);
     const KrylovVecs kv{L.cs_xu, nf, w.c_r, w.c_p, w.c_w, w.sc_c};
-    LAUNCH_B(fill_kernel<double>, nf, vs, s, nf, vs, nf, kv.x, 0.0);
-    LAUNCH_B(pcg_init_kernel, nf, vs, s, nf, vs, nf, (const double *)L.cs_bu, nf, (const double *)nullptr,
-             (const double *)L.cs_dinv, (const double *)L.cs_one, kv.r, kv.p, (float *)nullptr, w.partial,
-             w.pst, 1);
-    LAUNCH_1B(fin_init_kernel, vs, s, vs, (const double *)w.partial, w.pst, (int64_t)red_grid(nf), kv.sc,
+    LAUNCH_NB(fill_kernel<double>, nf, vs, nf, kv.x, 0.0);
+    LAUNCH_NB(pcg_init_kernel, nf, vs, nf, (const double *)L.cs_bu, nf, (const double *)nullptr,
+              (const double *)L.cs_dinv, (const double *)L.cs_one, kv.r, kv.p, (float *)nullptr, w.partial,
+              w.pst, 1);
+    LAUNCH_1B(fin_init_kernel, vs, s, vs, (const double *)w.partial, w.pst, (int64_t)nbv, kv.sc,
               cfg.coarse_tol, cfg.coarse_maxit, BbRef{});
-    const int nbv = red_grid(nf);
-    const int nbax = red_grid(nf * kCsrLanes);
+    // one row per group of lanes where the partial buffers allow (a row's
+    // loads are a dependent chain, so rows are not stacked on a thread)
+    const int nbax = (int)std::max<int64_t>(
+        1, std::min<int64_t>((nf * kCsrLanes + kRB - 1) / kRB, kMaxRedBlocks));
     for (int it = 1; it <= cfg.coarse_maxit; ++it) {
         const int parity = (it - 1) & 1;
-        LAUNCH_B(csr_spmv_dot_kernel, nf * kCsrLanes, vs, s, nf, vs, nf, (const int32_t *)L.cs_row,
-                 (const int32_t *)L.cs_col, (const double *)L.cs_val, (const double *)kv.p, kv.w,
-                 w.partial_ax, w.pst_ax, (const KrylovScalars *)kv.sc);
-        LAUNCH_B(pcg_update_fused_kernel, nf, vs, s, nf, vs, nf, kv.ldx, kv.sc, parity,
-                 (const double *)w.partial_ax, w.pst_ax, (int64_t)nbax, (const double *)kv.p,
-                 (const double *)kv.w, (const double *)L.cs_dinv, (const double *)L.cs_one, kv.x, kv.r,
-                 w.partial, w.pst);
-        LAUNCH_B(pcg_p_fused_kernel, nf, vs, s, nf, vs, nf, kv.sc, parity, it, (const double *)w.partial,
-                 w.pst, (int64_t)nbv, (const double *)L.cs_dinv, (const double *)kv.r, kv.p);
+        hipLaunchKernelGGL(csr_spmv_dot_kernel, dim3((unsigned)nbax, (unsigned)vs.n), dim3(kRB), 0, s, nf, vs,
+                           nf, (const int32_t *)L.cs_row, (const int32_t *)L.cs_col, (const double *)L.cs_val,
+                           (const double *)kv.p, kv.w, w.partial_ax, w.pst_ax, (const KrylovScalars *)kv.sc);
+        SEM_HIP(hipGetLastError());
+        LAUNCH_NB(pcg_update_fused_kernel, nf, vs, nf, kv.ldx, kv.sc, parity, (const double *)w.partial_ax,
+                  w.pst_ax, (int64_t)nbax, (const double *)kv.p, (const double *)kv.w,
+                  (const double *)L.cs_dinv, (const double *)L.cs_one, kv.x, kv.r, w.partial, w.pst);
+        LAUNCH_NB(pcg_p_fused_kernel, nf, vs, nf, kv.sc, parity, it, (const double *)w.partial, w.pst,
+                  (int64_t)nbv, (const double *)L.cs_dinv, (const double *)kv.r, kv.p);
     }
+#undef LAUNCH_NB
     LAUNCH_B(csr_scatter_kernel, n, vs, s, n, vs, (const int32_t *)L.cs_uid, (const double *)L.cs_xu, nf, x, n);
     return SEM_OK;
 }
