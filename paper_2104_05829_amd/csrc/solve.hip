@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "sem_internal.h"
+#include "coarse_csr.h"
 
 namespace semx {
 
@@ -1456,65 +1457,12 @@ static int build_coarse_csr(sem_handle h, double h1, double h2, hipStream_t s)
             if (W[l] > 0.0) uid[l] = uid[first[l]];
     }
     const int64_t nf = (int64_t)rep.size();
-    // CSR structure: the columns of a row are the free nodes that share an
-    // element with it (each row's list from its elements, sorted, duplicates
-    // dropped); the values are then summed per (row, col) in element order
-    // (element, then row point, then column point), the order a sort of all
-    // element-matrix entries by (row, col, element position) would give
-    std::vector<int32_t> row((size_t)nf + 1, 0), col;
-    std::vector<double> val, dinv((size_t)nf, 0.0), one((size_t)nf, 1.0);
-    {
-        std::vector<int64_t> cnt((size_t)nf + 1, 0);
-        for (int64_t e = 0; e < E; ++e) {
-            int nfe = 0;
-            for (int q = 0; q < np; ++q) nfe += uid[(size_t)e * np + q] >= 0;
-            for (int q = 0; q < np; ++q) {
-                const int32_t rq = uid[(size_t)e * np + q];
-                if (rq >= 0) cnt[(size_t)rq + 1] += nfe;
-            }
-        }
-        for (int64_t r = 0; r < nf; ++r) cnt[(size_t)r + 1] += cnt[(size_t)r];
-        std::vector<int32_t> all((size_t)cnt[(size_t)nf]);
-        std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-        for (int64_t e = 0; e < E; ++e)
-            for (int q = 0; q < np; ++q) {
-                const int32_t rq = uid[(size_t)e * np + q];
-                if (rq < 0) continue;
-                for (int pt = 0; pt < np; ++pt) {
-                    const int32_t cp = uid[(size_t)e * np + pt];
-                    if (cp >= 0) all[(size_t)fill[(size_t)rq]++] = cp;
-                }
-            }
-        col.reserve(all.size());
-        for (int64_t r = 0; r < nf; ++r) {
-            auto b = all.begin() + cnt[(size_t)r], en = all.begin() + cnt[(size_t)r + 1];
-            std::sort(b, en);
-            en = std::unique(b, en);
-            col.insert(col.end(), b, en);
-            row[(size_t)r + 1] = (int32_t)col.size();
-        }
-    }
-    val.assign(col.size(), 0.0);
-    for (int64_t e = 0; e < E; ++e)
-        for (int q = 0; q < np; ++q) {
-            const int32_t rq = uid[(size_t)e * np + q];
-            if (rq < 0) continue;
-            const int32_t *cb = col.data() + row[(size_t)rq], *ce = col.data() + row[(size_t)rq + 1];
-            for (int pt = 0; pt < np; ++pt) {
-                const int32_t cp = uid[(size_t)e * np + pt];
-                if (cp < 0) continue;
-                val[(size_t)(std::lower_bound(cb, ce, cp) - col.data())] += Ae[((size_t)e * np + q) * np + pt];
-            }
-        }
-    for (int64_t r = 0; r < nf; ++r) {
-        const int32_t *cb = col.data() + row[(size_t)r], *ce = col.data() + row[(size_t)r + 1];
-        const int32_t *d = std::lower_bound(cb, ce, (int32_t)r);
-        const double diag = (d != ce && *d == r) ? val[(size_t)(d - col.data())] : 0.0;
-        if (!(diag > 0.0)) {
-            set_error("coarse operator: nonpositive diagonal at node %lld", (long long)r);
-            return SEM_EBREAKDOWN;
-        }
-        dinv[(size_t)r] = 1.0 / diag;
+    std::vector<int32_t> row, col;
+    std::vector<double> val, dinv, one((size_t)nf, 1.0);
+    const int64_t bad = assemble_free_csr(E, np, nf, uid.data(), Ae.data(), row, col, val, dinv);
+    if (bad >= 0) {
+        set_error("coarse operator: nonpositive diagonal at node %lld", (long long)bad);
+        return SEM_EBREAKDOWN;
     }
     auto up = [&](void **dst, const void *src, size_t bytes) -> int {
         SEM_HIP(hipMalloc(dst, bytes > 0 ? bytes : 8));
