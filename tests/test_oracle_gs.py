@@ -45,8 +45,12 @@ def test_multiplicity_and_maps(shape, N):
         assert np.all(g[grp] == g[grp[0]]) and np.all(np.diff(grp) > 0)
 
 
-def test_c1_counts_match_survey_derivation():
-    """4x4x4 elements, N=7: 24,389 unique, 6,813 shared globals, 15,192 copies."""
+def test_c1_counts_match_closed_forms():
+    """4x4x4 elements, N=7 (29 nodes per direction, internal element planes at
+    indices 7, 14, 21): unique nodes 29^3 = 24,389; shared nodes (on at least
+    one internal plane) 29^3 - 26^3 = 6,813; their copies, a node on m internal
+    planes having 2^m, sum_m C(3,m) 3^m 26^(3-m) 2^m = 15,192; free nodes
+    under the Dirichlet box 27^3 = 19,683."""
     xi, _ = oracle.gll(7)
     m = inputs.box_mesh(4, 4, 4, xi)
     perm, offs = oracle.gs_maps(m.gid)
