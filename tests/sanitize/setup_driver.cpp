@@ -18,7 +18,7 @@
 #include "../../include/sem.h"
 
 namespace semx {
-// the library's error hook (defined in api.hip, which is not part of this build)
+// the library's error hook (defined in api.hip, which this test executable does not link)
 void set_error(const char *fmt, ...)
 {
     va_list ap;
