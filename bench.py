@@ -552,6 +552,7 @@ def bench_advect(args, torch, sem_mod, inputs):
     nq, E = N + 1, s.E
     nbytes = E * (3 * 2 * 8 * nq ** 3 + 3 * 8 * M ** 3)
     flops = E * 3 * advect_flops(nq, M)
+    out_h = out.cpu().numpy() if not args.no_cpu else None
     s.free()
     gbs = nbytes / (ms * 1e-3) / 1e9
     tfs = flops / (ms * 1e-3) / 1e12
@@ -571,9 +572,16 @@ def bench_advect(args, torch, sem_mod, inputs):
             for f in range(3):
                 oadv.advect(N, M, ctr, c[f][sl])
             t2 = time.perf_counter()
+        # the library's result on the same elements against the oracle's
+        # (max-norm error relative to the oracle's max per field)
+        errs = []
+        for f in range(3):
+            ref = oadv.advect(N, M, ctr, c[f][sl])
+            errs.append(float(np.max(np.abs(out_h[f][sl] - ref)) / np.max(np.abs(ref))))
         cpu = {"kind": "oracle", "cores": 1, "sample": f"first {ns} elements, numpy one thread, scaled by {E // ns}",
                "ms_advect_3_fields_scaled": round((t2 - t1) * 1e3 * E / ns, 1),
-               "ms_velocity_transform_scaled": round((t1 - t0) * 1e3 * E / ns, 1)}
+               "ms_velocity_transform_scaled": round((t1 - t0) * 1e3 * E / ns, 1),
+               "max_rel_err_vs_oracle": [float(f"{e_:.3e}") for e_ in errs]}
     return {"cpu_oracle": cpu, "workload": f"{ne}x{ne}x{ne} deformed box, N=7, Gauss rule M={M} per direction "
                         "(exact for degree 3N), the 3 velocity components advected by the velocity "
                         "(Taylor-Green-type vortex), one sem_advect call",
